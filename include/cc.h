@@ -1,0 +1,210 @@
+/*
+ * cc.h — C ABI of the MI355X colour-coding tree counter (libcc.so).
+ *
+ * The library counts colourful embeddings of a tree template T (k vertices) in an undirected
+ * graph G on one AMD MI355X (gfx950) GPU, following the colour-coding method of Section 2.1 of
+ * Chen et al., "High-Performance Massive Subgraph Counting using Pipelined Adaptive-Group
+ * Communication" (2018): colour G at random with k colours (Algorithm 1, the colouring loop),
+ * partition T recursively into active/passive sub-templates (Section 2.1, Figure 1(a); Algorithm 1,
+ * "Partition T into subtrees"), evaluate the dynamic program of Eq. 1 bottom-up, sum the per-vertex
+ * counts at the full template (Algorithm 1, Eq. 3), and scale to an estimate of #emb(T, G)
+ * (Section 2, "Subgraph-counting problem"; the colourful probability k!/k^k of Section 2.1).
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only. "dev" pointers are device (HBM) addresses on the current HIP device;
+ *     "host" pointers are ordinary host memory. `stream` is a hipStream_t passed as void*
+ *     (NULL = the null stream).
+ *   - The caller owns every device buffer it passes (graph arrays, colours, workspaces, outputs)
+ *     and keeps it alive until work queued on `stream` that uses it has finished. The library
+ *     never frees caller memory.
+ *   - Opaque handles (cc_plan, cc_graph) are owned by the library and freed by their destroy
+ *     call; they must outlive the stream work that uses them.
+ *   - Every call returns a cc_status. On failure nothing has been launched, and cc_last_error()
+ *     returns a message (thread-local, valid until the next call on the same thread).
+ *     Argument and shape errors are detected on the host before any launch. Faults raised
+ *     asynchronously by kernels surface as CC_EDEVICE from a later call, or at the caller's sync.
+ *   - No exception, abort or exit crosses this interface.
+ *   - Graph format: CSR with int64 row offsets (n+1 entries) and int32 columns (nnz entries),
+ *     rows sorted, no self-loops, no duplicates, symmetric (Section 2: G is undirected; an edge
+ *     is stored in both directions).
+ *   - Count values are IEEE double. They are exact integers when below 2^53. Results are
+ *     deterministic: the reduction order of every entry is fixed by the plan and the graph's
+ *     work split, never by the batch it runs in.
+ */
+#ifndef CC_H
+#define CC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CC_OK = 0,
+    CC_EINVAL = -1,    /* malformed argument: not a tree, bad CSR, null pointer, size mismatch */
+    CC_ERANGE = -2,    /* k outside [1, CC_MAX_K], or a size the kernels do not support */
+    CC_ENOMEM = -3,    /* host allocation failed */
+    CC_ENOSPC = -4,    /* the caller's workspace is smaller than the size the library asked for */
+    CC_EDEVICE = -5,   /* a HIP runtime call failed (launch, copy, or an earlier kernel fault) */
+    CC_EINTERNAL = -6
+} cc_status;
+
+#define CC_MAX_K 16
+
+/* ------------------------------------------------------------------------------------------ */
+/* Errors                                                                                      */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* cc_last_error(void);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Load tree template (Section 2.1: the template T, its root rho(T) and the recursive split    */
+/* into active T' and passive T'' sub-templates; Algorithm 1, "Partition T into subtrees")    */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct cc_plan cc_plan;
+
+/* flags for cc_plan_create */
+#define CC_PLAN_CENTRE_SMALLEST 1u  /* root = centre, attach children smallest subtree first
+                                       (the fixed reference partition used for bookkeeping) */
+
+/*
+ * k in [1, CC_MAX_K]; edges (host) = 2*(k-1) int32 vertex ids in [0, k) forming a tree.
+ * root in [0, k) fixes the template vertex that the per-vertex counts refer to; root = -1 lets
+ * the planner choose the cheapest root (the total X does not depend on the root or the
+ * partition). Returns CC_ERANGE for k out of range, CC_EINVAL if the edges are not a tree.
+ * The plan is host-only until cc_plan_bind_device.
+ */
+cc_status cc_plan_create(int32_t k, const int32_t* edges_host, int32_t root, uint32_t flags,
+                         cc_plan** out);
+
+typedef struct {
+    int32_t k;
+    int32_t root;
+    int32_t n_splits;                 /* number of sub-template splits (k-1) */
+    double aut;                       /* |Aut(T)|, the automorphism count of T */
+    int64_t units_per_edge;           /* colour-set-edge units per directed CSR entry, counted on
+                                         the reference partition: sum over splits of C(k,p), p the
+                                         passive size (1 for p = 1) */
+    int64_t table3_memory;            /* sum of C(k,|T_i|) and of C(k,|T_i|) C(|T_i|,|T_i'|) over */
+    int64_t table3_compute;           /*   this plan's split sub-templates other than T itself
+                                           (the bookkeeping of the paper's Table 3) */
+    int64_t gather_doubles_per_edge;  /* doubles read per CSR entry over all splits (this plan) */
+    int64_t combine_fma_per_vertex;   /* multiply-adds per vertex over all splits (this plan) */
+    int64_t peak_live_columns;        /* widest sum of live per-vertex table columns (doubles) */
+    size_t device_bytes;              /* size of the plan's device constants (cc_plan_bind_device) */
+} cc_plan_info;
+
+cc_status cc_plan_info_get(const cc_plan* plan, cc_plan_info* out);
+
+/* Sub-template sizes of split i in execution order: *s = |T_i|, *a = |T_i'|, *p = |T_i''|. */
+cc_status cc_plan_split_get(const cc_plan* plan, int32_t i, int32_t* s, int32_t* a, int32_t* p);
+
+/*
+ * Copy the plan's constant tables (colour-set split lists and neighbour fold maps) into the
+ * caller's device buffer `dev` of at least info.device_bytes bytes, on `stream`, and remember it.
+ * Must be called once before the plan is used by cc_count*; calling it again rebinds.
+ */
+cc_status cc_plan_bind_device(cc_plan* plan, void* dev, size_t bytes, void* stream);
+
+void cc_plan_destroy(cc_plan* plan);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Load CSR graph                                                                               */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct cc_graph cc_graph;
+
+/* work-split tuning (the degree split of Section 3.3, Algorithm 4, mapped to wavefronts) */
+typedef struct {
+    int32_t hub_threshold;  /* rows with more neighbours than this are cut into chunks (0 = auto) */
+    int32_t chunk;          /* neighbours per chunk of a cut row (0 = auto; multiple of 64) */
+} cc_tuning;
+
+/* flags for cc_graph_prepare */
+#define CC_GRAPH_TRUST 1u   /* skip the device-side CSR validation */
+
+/* Upper bound of the graph workspace (device bytes) for a graph of n vertices and nnz entries. */
+cc_status cc_graph_workspace_bytes(int64_t n, int64_t nnz, const cc_tuning* tuning, size_t* bytes);
+
+/*
+ * Prepare a graph whose CSR lives in caller device memory (row_ptr_dev: n+1 int64,
+ * col_dev: nnz int32). Unless CC_GRAPH_TRUST is set, a validation kernel checks that the rows are
+ * sorted, in range, free of self-loops and duplicates, and symmetric (CC_EINVAL otherwise).
+ * Builds the per-graph work lists (light rows, cut rows and their chunks) into `ws_dev`.
+ * Synchronises `stream` once (the row offsets are read back to the host to cut rows).
+ * The CSR and the workspace must stay alive and unchanged while the graph handle is used.
+ */
+cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, const int32_t* col_dev,
+                           void* ws_dev, size_t ws_bytes, const cc_tuning* tuning, uint32_t flags,
+                           void* stream, cc_graph** out);
+
+typedef struct {
+    int64_t n, nnz;
+    int64_t max_degree;
+    int64_t n_light, n_hubs, n_chunks;
+    int32_t hub_threshold, chunk;
+} cc_graph_info;
+
+cc_status cc_graph_info_get(const cc_graph* g, cc_graph_info* out);
+
+void cc_graph_release(cc_graph* g);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Colour (Algorithm 1: every vertex picks a colour in {1..k} uniformly at random)             */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * colours_dev[b*n + v] = colour of v in colouring (first_iter + b), for b in [0, B):
+ *   h = mix64(mix64(seed + 0x9E3779B97F4A7C15*(iter+1)) + 0xD1B54A32D192ED03*(v+1)),
+ *   colour = floor(k * h / 2^64)
+ * where mix64 is the SplitMix64 finaliser. colours_dev holds B*n bytes (caller-owned).
+ */
+cc_status cc_color(const cc_graph* g, int32_t k, uint64_t seed, uint64_t first_iter, int32_t B,
+                   uint8_t* colours_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Count (Algorithm 1: the dynamic program of Eq. 1 over the partition, then Eq. 3's sum)      */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Device workspace needed by cc_count for this plan on this graph (independent of B). */
+cc_status cc_count_workspace_bytes(const cc_plan* plan, const cc_graph* g, size_t* bytes);
+
+/*
+ * For b in [0, B): X_dev[b] = number of colourful labelled embeddings of T in G under colouring
+ * colours_dev + b*n (values in [0, k)), i.e. the number of injective maps phi : V_T -> V_G that
+ * keep every template edge and give the k template vertices k different colours.
+ * vertex_dev (optional, may be NULL): B*n doubles; vertex_dev[b*n + v] = the number of those maps
+ * with phi(root) = v, root as reported by cc_plan_info.
+ * The colourings are processed one after another on `stream`, reusing the workspace.
+ */
+cc_status cc_count(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
+                   void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Estimate (Algorithm 1, Eq. 3 and the final averaging; Section 2.1 colourful probability)    */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * Host-side: *estimate = mean_b(X_host[b]) * k^k / k! / |Aut(T)|, evaluated in long double and
+ * rounded once; *std_err = the standard error of that mean (0 for B = 1).
+ */
+cc_status cc_estimate(const cc_plan* plan, const double* X_host, int32_t B, double* estimate,
+                      double* std_err);
+
+/*
+ * Host-side (epsilon, delta) estimate of Algorithm 1's last step: split the B values into
+ * `groups` groups of equal size (B must be a multiple of groups), average each, and return the
+ * median of the group means, scaled as in cc_estimate.
+ */
+cc_status cc_estimate_median_of_means(const cc_plan* plan, const double* X_host, int32_t B,
+                                      int32_t groups, double* estimate);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CC_H */

@@ -1,0 +1,292 @@
+"""MI355X colour-coding tree counter: thin Python binding over libcc.so (include/cc.h).
+
+The binding only marshals arguments: device memory comes from PyTorch tensors, streams are
+PyTorch's current HIP stream, and every step of the counting path runs in the library's HIP
+kernels. There is no CPU fallback: if libcc.so is missing or a tensor is not on the GPU, the
+calls raise.
+
+Verbs (Section 2 "Subgraph-counting problem" and Algorithm 1 of the paper):
+  Plan(edges)           load tree template (partition into active/passive sub-templates)
+  Graph(row_ptr, col)   load CSR graph (validated, work lists built)
+  colour(graph, k, ..)  random colourings
+  count(plan, graph, colours)   colourful embedding counts X per colouring
+  estimate(plan, X)     mean(X) * k^k / k! / |Aut(T)|
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcc.so")
+
+CC_PLAN_CENTRE_SMALLEST = 1
+CC_GRAPH_TRUST = 1
+
+_STATUS = {0: "CC_OK", -1: "CC_EINVAL", -2: "CC_ERANGE", -3: "CC_ENOMEM", -4: "CC_ENOSPC",
+           -5: "CC_EDEVICE", -6: "CC_EINTERNAL"}
+
+
+class CCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("root", ctypes.c_int32), ("n_splits", ctypes.c_int32),
+                ("aut", ctypes.c_double), ("units_per_edge", ctypes.c_int64),
+                ("table3_memory", ctypes.c_int64), ("table3_compute", ctypes.c_int64),
+                ("gather_doubles_per_edge", ctypes.c_int64), ("combine_fma_per_vertex", ctypes.c_int64),
+                ("peak_live_columns", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+
+
+class _GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
+                ("n_light", ctypes.c_int64), ("n_hubs", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
+                ("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+
+EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
+           "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
+           "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
+           "cc_estimate", "cc_estimate_median_of_means"]
+
+
+@lru_cache(maxsize=1)
+def lib() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                           "python paper_1804_09764_amd/_build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32, I64, U32, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "cc_last_error": (ctypes.c_char_p, []),
+        "cc_plan_create": (ctypes.c_int, [I32, P, I32, U32, ctypes.POINTER(P)]),
+        "cc_plan_info_get": (ctypes.c_int, [P, ctypes.POINTER(_PlanInfo)]),
+        "cc_plan_split_get": (ctypes.c_int, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                             ctypes.POINTER(I32)]),
+        "cc_plan_bind_device": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
+        "cc_plan_destroy": (None, [P]),
+        "cc_graph_workspace_bytes": (ctypes.c_int, [I64, I64, P, ctypes.POINTER(ctypes.c_size_t)]),
+        "cc_graph_prepare": (ctypes.c_int, [I64, I64, P, P, P, ctypes.c_size_t, P, U32, P,
+                                            ctypes.POINTER(P)]),
+        "cc_graph_info_get": (ctypes.c_int, [P, ctypes.POINTER(_GraphInfo)]),
+        "cc_graph_release": (None, [P]),
+        "cc_color": (ctypes.c_int, [P, I32, U64, U64, I32, P, P]),
+        "cc_count_workspace_bytes": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_size_t)]),
+        "cc_count": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
+        "cc_estimate": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
+        "cc_estimate_median_of_means": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ctypes.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CCError(rc, lib().cc_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class PlanInfo:
+    k: int
+    root: int
+    n_splits: int
+    aut: float
+    units_per_edge: int
+    table3_memory: int
+    table3_compute: int
+    gather_doubles_per_edge: int
+    combine_fma_per_vertex: int
+    peak_live_columns: int
+    device_bytes: int
+
+
+class Plan:
+    """A tree template and its partition (host); `bind()` uploads its constant tables to the GPU."""
+
+    def __init__(self, edges, root: int = -1, flags: int = 0, bind: bool = True, device=None):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        self.edges = e
+        self.k = e.shape[0] + 1
+        h = ctypes.c_void_p()
+        _check(lib().cc_plan_create(self.k, e.ctypes.data if e.size else None, root, flags,
+                                    ctypes.byref(h)))
+        self._h = h
+        self._dev = None
+        inf = _PlanInfo()
+        _check(lib().cc_plan_info_get(self._h, ctypes.byref(inf)))
+        self.info = PlanInfo(*(getattr(inf, f[0]) for f in _PlanInfo._fields_))
+        self.splits = []
+        for i in range(self.info.n_splits):
+            s, a, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            _check(lib().cc_plan_split_get(self._h, i, ctypes.byref(s), ctypes.byref(a), ctypes.byref(p)))
+            self.splits.append((s.value, a.value, p.value))
+        if bind:
+            self.bind(device)
+
+    def bind(self, device=None, stream=None):
+        import torch
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = max(int(self.info.device_bytes), 256)
+        self._dev = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _check(lib().cc_plan_bind_device(self._h, ctypes.c_void_p(self._dev.data_ptr()), nbytes, _stream(stream)))
+        return self
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().cc_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+class Graph:
+    """A CSR graph resident on the GPU (int64 row_ptr, int32 col) with its prepared work lists."""
+
+    def __init__(self, row_ptr, col, hub_threshold: int = 0, chunk: int = 0, trust: bool = False,
+                 stream=None):
+        import torch
+        self.row_ptr = row_ptr
+        self.col = col
+        n = row_ptr.numel() - 1
+        nnz = col.numel()
+        self.n, self.nnz = n, nnz
+        tun = _Tuning(hub_threshold, chunk)
+        nb = ctypes.c_size_t()
+        _check(lib().cc_graph_workspace_bytes(n, nnz, ctypes.byref(tun), ctypes.byref(nb)))
+        self._ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=row_ptr.device)
+        h = ctypes.c_void_p()
+        _check(lib().cc_graph_prepare(n, nnz, _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+                                      _dev_ptr(col, torch.int32, "col") if nnz else None,
+                                      ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                      ctypes.byref(tun), CC_GRAPH_TRUST if trust else 0, _stream(stream),
+                                      ctypes.byref(h)))
+        self._h = h
+        gi = _GraphInfo()
+        _check(lib().cc_graph_info_get(self._h, ctypes.byref(gi)))
+        self.info = {f[0]: getattr(gi, f[0]) for f in _GraphInfo._fields_}
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col, device="cuda", **kw):
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int64)).to(device)
+        cl = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device)
+        return cls(rp, cl, **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().cc_graph_release(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def colour(graph: Graph, k: int, seed: int, first_iter: int = 0, B: int = 1, out=None, stream=None):
+    """B counter-based random colourings, uint8 tensor [B, n] on the graph's device."""
+    import torch
+    if out is None:
+        out = torch.empty((B, graph.n), dtype=torch.uint8, device=graph.row_ptr.device)
+    _check(lib().cc_color(graph.handle, k, seed, first_iter, B, _dev_ptr(out, torch.uint8, "colours"),
+                          _stream(stream)))
+    return out
+
+
+class Workspace:
+    """Caller-owned count workspace (reused across calls with the same plan/graph shapes)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+def count_workspace_bytes(plan: Plan, graph: Graph) -> int:
+    nb = ctypes.c_size_t()
+    _check(lib().cc_count_workspace_bytes(plan.handle, graph.handle, ctypes.byref(nb)))
+    return nb.value
+
+
+def count(plan: Plan, graph: Graph, colours, per_vertex: bool = False, workspace: Workspace | None = None,
+          out=None, vertex_out=None, stream=None):
+    """X[b] for each colouring row of `colours` ([B, n] uint8 on the GPU); float64 tensors."""
+    import torch
+    if colours.dim() == 1:
+        colours = colours.view(1, -1)
+    B = colours.shape[0]
+    if colours.shape[1] != graph.n:
+        raise ValueError("colours must be [B, n]")
+    dev = graph.row_ptr.device
+    ws = (workspace or Workspace()).get(count_workspace_bytes(plan, graph), dev)
+    X = out if out is not None else torch.empty(B, dtype=torch.float64, device=dev)
+    V = None
+    if per_vertex:
+        V = vertex_out if vertex_out is not None else torch.empty((B, graph.n), dtype=torch.float64, device=dev)
+    _check(lib().cc_count(plan.handle, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B,
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dev_ptr(X, torch.float64, "X"),
+                          _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
+    return (X, V) if per_vertex else X
+
+
+def estimate(plan: Plan, X) -> tuple[float, float]:
+    """mean(X) * k^k / k! / |Aut(T)| and its standard error (host)."""
+    x = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(-1))
+    est, se = ctypes.c_double(), ctypes.c_double()
+    _check(lib().cc_estimate(plan.handle, x.ctypes.data, len(x), ctypes.byref(est), ctypes.byref(se)))
+    return est.value, se.value
+
+
+def estimate_median_of_means(plan: Plan, X, groups: int) -> float:
+    x = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(-1))
+    est = ctypes.c_double()
+    _check(lib().cc_estimate_median_of_means(plan.handle, x.ctypes.data, len(x), groups, ctypes.byref(est)))
+    return est.value

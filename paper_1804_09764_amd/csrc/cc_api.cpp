@@ -1,0 +1,421 @@
+// Host side of the C ABI declared in include/cc.h: argument checking, workspace layout, work-list
+// construction and the launch sequence of one count.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cc_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+cc_status fail(cc_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+cc_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return CC_EDEVICE;
+}
+
+inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+inline int64_t pad32(int64_t n) { return (n + 31) / 32 * 32; }
+
+void resolve_tuning(int64_t nnz, const cc_tuning* t, int32_t* thr, int32_t* chunk) {
+    int32_t c = (t && t->chunk > 0) ? t->chunk : (nnz >= ((int64_t)1 << 28) ? 2048 : 512);
+    c = (c + 63) / 64 * 64;
+    int32_t h = (t && t->hub_threshold > 0) ? t->hub_threshold : 2 * c;
+    if (h < c) h = c;
+    *thr = h;
+    *chunk = c;
+}
+
+struct GraphLayout {
+    size_t flags_off, light_off, chunk_off, hub_off, total;
+};
+
+GraphLayout graph_layout(int64_t n, int64_t nnz, int32_t thr, int32_t chunk) {
+    GraphLayout L;
+    const int64_t max_hubs = nnz / ((int64_t)thr + 1) + 1;
+    const int64_t max_chunks = nnz / chunk + max_hubs;
+    L.flags_off = 0;
+    L.light_off = 256;
+    L.chunk_off = align256(L.light_off + (size_t)n * sizeof(int32_t));
+    L.hub_off = align256(L.chunk_off + (size_t)max_chunks * sizeof(cc::ChunkItem));
+    L.total = align256(L.hub_off + (size_t)max_hubs * sizeof(cc::HubItem));
+    return L;
+}
+
+struct CountLayout {
+    size_t arena_off, partial_off, root_off, red_off, ctr_off, total;
+    int64_t n_pad;
+};
+
+CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
+    CountLayout L;
+    L.n_pad = pad32(G->n);
+    L.arena_off = 0;
+    L.partial_off = align256((size_t)P->arena_cols * (size_t)L.n_pad * sizeof(double));
+    L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)P->max_stride_N * sizeof(double));
+    L.red_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * sizeof(double));
+    L.ctr_off = align256(L.red_off + 1024 * sizeof(double));
+    L.total = align256(L.ctr_off + (2 * P->splits.size() + 2) * sizeof(unsigned));
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cc_last_error(void) { return g_err.c_str(); }
+
+cc_status cc_plan_create(int32_t k, const int32_t* edges_host, int32_t root, uint32_t flags, cc_plan** out) {
+    if (!out) return fail(CC_EINVAL, "out is NULL");
+    *out = nullptr;
+    cc_plan* P = new (std::nothrow) cc_plan();
+    if (!P) return fail(CC_ENOMEM, "plan allocation failed");
+    std::string err;
+    cc_status st;
+    try {
+        st = cc::plan_build(k, edges_host, root, flags, P, &err);
+    } catch (const std::bad_alloc&) {
+        st = CC_ENOMEM;
+        err = "host allocation failed while planning";
+    } catch (...) {
+        st = CC_EINTERNAL;
+        err = "planner failed";
+    }
+    if (st != CC_OK) {
+        delete P;
+        return fail(st, err);
+    }
+    *out = P;
+    g_err.clear();
+    return CC_OK;
+}
+
+cc_status cc_plan_info_get(const cc_plan* P, cc_plan_info* o) {
+    if (!P || !o) return fail(CC_EINVAL, "NULL argument");
+    o->k = P->k;
+    o->root = P->root;
+    o->n_splits = (int32_t)P->splits.size();
+    o->aut = P->aut;
+    o->units_per_edge = P->units_per_edge;
+    o->table3_memory = P->t3_memory;
+    o->table3_compute = P->t3_compute;
+    o->gather_doubles_per_edge = P->gather_per_edge;
+    o->combine_fma_per_vertex = P->combine_per_vertex;
+    o->peak_live_columns = P->peak_live_cols;
+    o->device_bytes = P->consts.size();
+    return CC_OK;
+}
+
+cc_status cc_plan_split_get(const cc_plan* P, int32_t i, int32_t* s, int32_t* a, int32_t* p) {
+    if (!P || !s || !a || !p) return fail(CC_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int32_t)P->splits.size()) return fail(CC_ERANGE, "split index out of range");
+    *s = P->splits[i].s;
+    *a = P->splits[i].a;
+    *p = P->splits[i].p;
+    return CC_OK;
+}
+
+cc_status cc_plan_bind_device(cc_plan* P, void* dev, size_t bytes, void* stream) {
+    if (!P || !dev) return fail(CC_EINVAL, "NULL argument");
+    if (bytes < P->consts.size()) return fail(CC_ENOSPC, "device buffer smaller than info.device_bytes");
+    hipError_t e = hipMemcpyAsync(dev, P->consts.data(), P->consts.size(), hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan constants)");
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(plan constants)");
+    P->dev = dev;
+    P->dev_bytes = bytes;
+    return CC_OK;
+}
+
+void cc_plan_destroy(cc_plan* P) { delete P; }
+
+cc_status cc_graph_workspace_bytes(int64_t n, int64_t nnz, const cc_tuning* tuning, size_t* bytes) {
+    if (!bytes || n < 0 || nnz < 0) return fail(CC_EINVAL, "bad argument");
+    if (n >= ((int64_t)1 << 31)) return fail(CC_ERANGE, "n must be below 2^31");
+    int32_t thr, chunk;
+    resolve_tuning(nnz, tuning, &thr, &chunk);
+    *bytes = graph_layout(n, nnz, thr, chunk).total;
+    return CC_OK;
+}
+
+cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, const int32_t* col_dev,
+                           void* ws_dev, size_t ws_bytes, const cc_tuning* tuning, uint32_t flags,
+                           void* stream, cc_graph** out) {
+    if (!out) return fail(CC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || nnz < 0 || !row_ptr_dev || (nnz > 0 && !col_dev) || !ws_dev)
+        return fail(CC_EINVAL, "bad graph arguments");
+    if (n >= ((int64_t)1 << 31)) return fail(CC_ERANGE, "n must be below 2^31");
+    int32_t thr, chunk;
+    resolve_tuning(nnz, tuning, &thr, &chunk);
+    GraphLayout L = graph_layout(n, nnz, thr, chunk);
+    if (ws_bytes < L.total) return fail(CC_ENOSPC, "graph workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)ws_dev;
+    unsigned* dflags = (unsigned*)(ws + L.flags_off);
+    hipError_t e;
+    // row offsets are checked on the host first, so that the validation kernel only follows
+    // offsets that stay inside col
+    std::vector<int64_t> rp((size_t)n + 1);
+    e = hipMemcpyAsync(rp.data(), row_ptr_dev, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "row offset readback");
+    if (rp[0] != 0 || rp[n] != nnz) return fail(CC_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] = nnz");
+    for (int64_t v = 0; v < n; ++v)
+        if (rp[v + 1] < rp[v]) return fail(CC_EINVAL, "row offsets decrease");
+    if (!(flags & CC_GRAPH_TRUST)) {
+        e = cc::launch_fill_u32(dflags, 1, 0u, st);
+        if (e != hipSuccess) return hip_fail(e, "validation launch");
+        e = cc::launch_validate(row_ptr_dev, col_dev, n, nnz, dflags, st);
+        if (e != hipSuccess) return hip_fail(e, "validation launch");
+        unsigned hf = 0;
+        e = hipMemcpyAsync(&hf, dflags, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "validation readback");
+        if (hf) {
+            std::string m = "CSR validation failed:";
+            if (hf & 1u) m += " column out of range;";
+            if (hf & 2u) m += " self-loop;";
+            if (hf & 4u) m += " unsorted or duplicate entries;";
+            if (hf & 8u) m += " not symmetric;";
+            return fail(CC_EINVAL, m);
+        }
+    }
+    std::vector<int32_t> light;
+    std::vector<cc::ChunkItem> chunks;
+    std::vector<cc::HubItem> hubs;
+    int64_t maxdeg = 0;
+    light.reserve((size_t)n);
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t d = rp[v + 1] - rp[v];
+        maxdeg = std::max(maxdeg, d);
+        if (d > thr) {
+            cc::HubItem h;
+            h.v = (int32_t)v;
+            h.first_chunk = (int64_t)chunks.size();
+            for (int64_t b = rp[v]; b < rp[v + 1]; b += chunk) {
+                cc::ChunkItem c;
+                c.beg = b;
+                c.v = (int32_t)v;
+                c.len = (int32_t)std::min<int64_t>(chunk, rp[v + 1] - b);
+                chunks.push_back(c);
+            }
+            h.n_chunks = (int32_t)(chunks.size() - h.first_chunk);
+            hubs.push_back(h);
+        } else {
+            light.push_back((int32_t)v);
+        }
+    }
+    // heaviest rows first so that long items start early
+    std::stable_sort(light.begin(), light.end(), [&](int32_t a, int32_t b) {
+        return (rp[a + 1] - rp[a]) > (rp[b + 1] - rp[b]);
+    });
+    // chunk items interleaved across cut rows is unnecessary: each chunk is bounded by `chunk`
+    cc_graph* G = new (std::nothrow) cc_graph();
+    if (!G) return fail(CC_ENOMEM, "graph allocation failed");
+    G->n = n;
+    G->nnz = nnz;
+    G->max_degree = maxdeg;
+    G->row_ptr = row_ptr_dev;
+    G->col = col_dev;
+    G->light = (int32_t*)(ws + L.light_off);
+    G->chunks = (cc::ChunkItem*)(ws + L.chunk_off);
+    G->hubs = (cc::HubItem*)(ws + L.hub_off);
+    G->n_light = (int64_t)light.size();
+    G->n_chunks = (int64_t)chunks.size();
+    G->n_hubs = (int64_t)hubs.size();
+    G->hub_threshold = thr;
+    G->chunk = chunk;
+    if (G->n_light + G->n_chunks >= ((int64_t)1 << 32)) {
+        delete G;
+        return fail(CC_ERANGE, "too many work items");
+    }
+    e = hipGetDevice(&G->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&G->n_cu, hipDeviceAttributeMultiprocessorCount, G->device);
+    if (e == hipSuccess && !light.empty())
+        e = hipMemcpyAsync(G->light, light.data(), light.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !chunks.empty())
+        e = hipMemcpyAsync(G->chunks, chunks.data(), chunks.size() * sizeof(cc::ChunkItem), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !hubs.empty())
+        e = hipMemcpyAsync(G->hubs, hubs.data(), hubs.size() * sizeof(cc::HubItem), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete G;
+        return hip_fail(e, "graph work-list upload");
+    }
+    *out = G;
+    return CC_OK;
+}
+
+cc_status cc_graph_info_get(const cc_graph* G, cc_graph_info* o) {
+    if (!G || !o) return fail(CC_EINVAL, "NULL argument");
+    o->n = G->n;
+    o->nnz = G->nnz;
+    o->max_degree = G->max_degree;
+    o->n_light = G->n_light;
+    o->n_hubs = G->n_hubs;
+    o->n_chunks = G->n_chunks;
+    o->hub_threshold = G->hub_threshold;
+    o->chunk = G->chunk;
+    return CC_OK;
+}
+
+void cc_graph_release(cc_graph* G) { delete G; }
+
+cc_status cc_color(const cc_graph* G, int32_t k, uint64_t seed, uint64_t first_iter, int32_t B,
+                   uint8_t* colours_dev, void* stream) {
+    if (!G || (!colours_dev && B > 0 && G->n > 0)) return fail(CC_EINVAL, "NULL argument");
+    if (k < 1 || k > CC_MAX_K) return fail(CC_ERANGE, "k must be in [1, 16]");
+    if (B < 0) return fail(CC_EINVAL, "B must be >= 0");
+    hipError_t e = cc::launch_colour(seed, first_iter, G->n, k, B, colours_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "colour launch");
+    return CC_OK;
+}
+
+cc_status cc_count_workspace_bytes(const cc_plan* P, const cc_graph* G, size_t* bytes) {
+    if (!P || !G || !bytes) return fail(CC_EINVAL, "NULL argument");
+    *bytes = count_layout(P, G).total;
+    return CC_OK;
+}
+
+cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_dev, int32_t B, void* ws_dev,
+                   size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream) {
+    if (!P || !G) return fail(CC_EINVAL, "NULL plan or graph");
+    if (B < 0) return fail(CC_EINVAL, "B must be >= 0");
+    if (B == 0) return CC_OK;
+    if (!X_dev || !ws_dev || (G->n > 0 && !colours_dev)) return fail(CC_EINVAL, "NULL buffer");
+    if (!P->splits.empty() && !P->dev) return fail(CC_EINVAL, "plan not bound to device memory");
+    CountLayout L = count_layout(P, G);
+    if (ws_bytes < L.total) return fail(CC_ENOSPC, "count workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)ws_dev;
+    double* arena = (double*)(ws + L.arena_off);
+    double* partial = (double*)(ws + L.partial_off);
+    double* red = (double*)(ws + L.red_off);
+    unsigned* ctr = (unsigned*)(ws + L.ctr_off);
+    const int64_t n = G->n;
+    const uint8_t* cdev = (const uint8_t*)P->dev;
+    hipError_t e = hipSuccess;
+    for (int32_t b = 0; b < B; ++b) {
+        double* root_out = vertex_dev ? vertex_dev + (int64_t)b * n : (double*)(ws + L.root_off);
+        if (n == 0) {
+            e = cc::launch_fill_f64(X_dev + b, 1, 0.0, st);
+            if (e != hipSuccess) return hip_fail(e, "fill");
+            continue;
+        }
+        const uint8_t* colour = colours_dev + (int64_t)b * n;
+        if (P->splits.empty()) {
+            // k = 1: every vertex roots exactly one map
+            e = cc::launch_fill_f64(root_out, n, 1.0, st);
+        } else {
+            e = cc::launch_fill_u32(ctr, (int64_t)(2 * P->splits.size()), 0u, st);
+            for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
+                const cc::Split& sp = P->splits[i];
+                cc::StepParamsHost h{};
+                h.row_ptr = G->row_ptr;
+                h.col = G->col;
+                h.colour = colour;
+                h.light = G->light;
+                h.chunks = G->chunks;
+                h.hubs = G->hubs;
+                h.n_light = G->n_light;
+                h.n_chunks = G->n_chunks;
+                h.n_hubs = G->n_hubs;
+                if (sp.pas >= 0) {
+                    const cc::Table& t = P->tables[sp.pas];
+                    h.P = arena + t.col_off * L.n_pad;
+                    h.pstride = t.stride;
+                }
+                if (sp.act >= 0) {
+                    const cc::Table& t = P->tables[sp.act];
+                    h.A = arena + t.col_off * L.n_pad;
+                    h.astride = t.stride;
+                }
+                if (sp.out >= 0) {
+                    const cc::Table& t = P->tables[sp.out];
+                    h.O = arena + t.col_off * L.n_pad;
+                    h.ostride = t.stride;
+                } else {
+                    h.O = root_out;
+                    h.ostride = 1;
+                }
+                h.partial = partial;
+                h.nstride = P->max_stride_N;
+                h.fold = sp.fold_off >= 0 ? (const uint16_t*)(cdev + sp.fold_off) : nullptr;
+                h.split = sp.split_off >= 0 ? (const uint32_t*)(cdev + sp.split_off) : nullptr;
+                h.k = P->k;
+                h.s = sp.s;
+                h.a = sp.a;
+                h.p = sp.p;
+                h.Wa = sp.Wa;
+                h.Wp = sp.Wp;
+                h.Ws = sp.Ws;
+                h.Nw = sp.Nw;
+                h.npairs = sp.npairs;
+                h.counters = ctr + 2 * i;
+                h.n_cu = G->n_cu;
+                e = cc::launch_split(h, st);
+            }
+        }
+        if (e == hipSuccess) e = cc::launch_reduce(root_out, n, red, X_dev + b, st);
+        if (e != hipSuccess) return hip_fail(e, "count launch");
+    }
+    return CC_OK;
+}
+
+static long double scale_factor(const cc_plan* P) {
+    long double s = 1.0L;
+    for (int i = 1; i <= P->k; ++i) s *= (long double)P->k / (long double)i;  // k^k / k!
+    return s / (long double)P->aut;
+}
+
+cc_status cc_estimate(const cc_plan* P, const double* X_host, int32_t B, double* estimate, double* std_err) {
+    if (!P || !X_host || !estimate) return fail(CC_EINVAL, "NULL argument");
+    if (B < 1) return fail(CC_EINVAL, "B must be >= 1");
+    long double m = 0.0L;
+    for (int32_t b = 0; b < B; ++b) m += (long double)X_host[b];
+    m /= (long double)B;
+    long double var = 0.0L;
+    for (int32_t b = 0; b < B; ++b) {
+        long double d = (long double)X_host[b] - m;
+        var += d * d;
+    }
+    const long double f = scale_factor(P);
+    *estimate = (double)(m * f);
+    if (std_err) *std_err = (B > 1) ? (double)(sqrtl(var / (long double)(B - 1) / (long double)B) * f) : 0.0;
+    return CC_OK;
+}
+
+cc_status cc_estimate_median_of_means(const cc_plan* P, const double* X_host, int32_t B, int32_t groups,
+                                      double* estimate) {
+    if (!P || !X_host || !estimate) return fail(CC_EINVAL, "NULL argument");
+    if (groups < 1 || B < groups || B % groups) return fail(CC_EINVAL, "B must be a positive multiple of groups");
+    const int32_t per = B / groups;
+    std::vector<long double> means((size_t)groups);
+    for (int32_t g = 0; g < groups; ++g) {
+        long double m = 0.0L;
+        for (int32_t i = 0; i < per; ++i) m += (long double)X_host[g * per + i];
+        means[(size_t)g] = m / (long double)per;
+    }
+    std::sort(means.begin(), means.end());
+    long double med = (groups % 2) ? means[(size_t)groups / 2]
+                                   : 0.5L * (means[(size_t)groups / 2 - 1] + means[(size_t)groups / 2]);
+    *estimate = (double)(med * scale_factor(P));
+    return CC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal declarations shared by the planner, the host API and the kernels of libcc.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cc.h"
+
+namespace cc {
+
+constexpr int kMaxK = CC_MAX_K;
+constexpr int kWave = 64;             // CDNA wavefront width
+constexpr uint16_t kNoSlot = 0xFFFF;  // fold map: this passive entry does not reach v
+
+int64_t binom(int n, int r);
+
+// One cut of a sub-template T_i (size s) into the active part T_i' (size a, keeps the root) and
+// the passive part T_i'' (size p, rooted at the cut child). Table widths are per vertex, in the
+// colour-anchored layout: a table for a sub-template of size t stores, for vertex v, the counts of
+// the colour sets S with col(v) in S, indexed by the colex rank of S \ {col(v)} over the k-1
+// other colours (re-numbered 0..k-2). Its width is W(t) = C(k-1, t-1).
+struct Split {
+    int s, a, p;
+    int act;        // table id of T_i' (-1: a single vertex, count 1 for its own colour)
+    int pas;        // table id of T_i'' (-1: a single vertex)
+    int out;        // table id of T_i (-2: the full template, one value per vertex)
+    int Wa, Wp, Ws; // anchored widths of T_i', T_i'', T_i
+    int Nw;         // width of the neighbour sum N(v, Q), |Q| = p, Q over the k-1 other colours
+    int npairs;     // C(s-1, p): splits of one output set
+    int64_t split_off;  // byte offset of the pair list in the device constants (-1 if a == 1)
+    int64_t fold_off;   // byte offset of the fold map in the device constants (-1 if p == 1)
+};
+
+struct Table {
+    int size;        // sub-template size t
+    int W;           // C(k-1, t-1)
+    int stride;      // row stride in doubles
+    int64_t col_off; // offset in columns (1 column = n_pad doubles) inside the table arena
+};
+
+}  // namespace cc
+
+struct cc_plan {
+    int k = 0;
+    int root = 0;
+    std::vector<int32_t> edges;
+    std::vector<cc::Split> splits;
+    std::vector<cc::Table> tables;
+    int64_t arena_cols = 0;   // peak columns of the table arena
+    int max_Nw = 0;           // widest neighbour-sum row over splits
+    int max_stride_N = 0;     // its padded stride
+    std::vector<uint8_t> consts;  // device constants, host copy
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    double aut = 1.0;
+    int64_t units_per_edge = 0;
+    int64_t t3_memory = 0, t3_compute = 0;
+    int64_t gather_per_edge = 0, combine_per_vertex = 0;
+    int64_t peak_live_cols = 0;
+};
+
+namespace cc {
+
+// work items of a prepared graph
+struct ChunkItem {
+    int64_t beg;     // first CSR entry of the chunk
+    int32_t v;       // row
+    int32_t len;     // number of entries (<= chunk)
+};
+
+struct HubItem {
+    int32_t v;
+    int32_t n_chunks;
+    int64_t first_chunk;
+};
+
+cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_plan* P,
+                     std::string* err);
+
+int pad_stride(int W);
+
+// arguments of one split launch (host side)
+struct StepParamsHost {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const uint8_t* colour;
+    const int32_t* light;
+    const ChunkItem* chunks;
+    const HubItem* hubs;
+    int64_t n_light, n_chunks, n_hubs;
+    const double* P;
+    const double* A;
+    double* O;
+    double* partial;
+    const uint16_t* fold;
+    const uint32_t* split;
+    int64_t pstride, astride, ostride, nstride;
+    int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
+    unsigned* counters;  // two work counters (split kernel, hub finish), zeroed before launch
+    int n_cu;
+};
+
+}  // namespace cc
+
+#include <hip/hip_runtime_api.h>
+namespace cc {
+hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_colour(uint64_t seed, uint64_t first_iter, int64_t n, int k, int B, uint8_t* out,
+                         hipStream_t st);
+int reduce_blocks_for(int64_t n);
+hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* out, hipStream_t st);
+hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                           unsigned* flags, hipStream_t st);
+hipError_t launch_split(const StepParamsHost& h, hipStream_t st);
+size_t split_lds_bytes(int Nw, int Wa, int a);
+}  // namespace cc
+
+struct cc_graph {
+    int64_t n = 0, nnz = 0, max_degree = 0;
+    const int64_t* row_ptr = nullptr;
+    const int32_t* col = nullptr;
+    int32_t* light = nullptr;        // device: light rows, heaviest first
+    cc::ChunkItem* chunks = nullptr; // device
+    cc::HubItem* hubs = nullptr;     // device
+    int64_t n_light = 0, n_chunks = 0, n_hubs = 0;
+    int32_t hub_threshold = 0, chunk = 0;
+    int device = 0;
+    int n_cu = 0;
+};

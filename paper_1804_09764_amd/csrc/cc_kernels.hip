@@ -1,0 +1,488 @@
+// HIP kernels of the colour-coding hot path (gfx950, wave64).
+//
+// One split of the dynamic program (Section 2.1, Eq. 1) is evaluated in its distributive form:
+//
+//   N(v, Q)  = sum_{u in N(v)} C(u, T'', Q)                         neighbour sum, |Q| = p
+//   C(v,T,S) = sum_{S1 subset S, |S1| = a} C(v, T', S1) * N(v, S \ S1)   combine
+//
+// which regroups the double sum of Eq. 1 (the neighbour loop moves inside, next to the passive
+// factor, because C(v, T', S1) does not depend on u).
+//
+// Tables use the colour-anchored layout: a sub-template's count C(v, T_i, S) is zero unless
+// col(v) is in S (the root of T_i sits on v), so row v stores only the sets containing col(v),
+// indexed by the colex rank of S \ {col(v)} over the k-1 other colours renumbered 0..k-2. A
+// neighbour u's passive row is written over the colours other than col(u); the fold map
+// M[col(u)][col(v)][j] moves its entry j to the index of the same set over the colours other
+// than col(v) (or drops it when the set contains col(v), which no term of the combine can use).
+// Neighbours with col(u) = col(v) contribute nothing and are skipped.
+//
+// Work split (the neighbour-list partitioning of Section 3.3, Algorithm 4, on wavefronts): every
+// row of at most `hub_threshold` entries is one work item processed by one wavefront; longer rows
+// are cut into chunks of `chunk` entries whose partial neighbour sums go to scratch and are added
+// in chunk order by a second kernel, so every entry has one fixed summation order (no atomics on
+// counts). Work items are handed out through a device counter to persistent workgroups.
+#include <hip/hip_runtime.h>
+
+#include "cc_internal.h"
+
+namespace cc {
+
+struct StepParams {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const uint8_t* colour;
+    const int32_t* light;
+    const ChunkItem* chunks;
+    const HubItem* hubs;
+    int64_t n_light, n_chunks, n_hubs;
+    const double* P;
+    const double* A;
+    double* O;
+    double* partial;
+    const uint16_t* fold;
+    const uint32_t* split;
+    int64_t pstride, astride, ostride, nstride;
+    int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
+    int lds_wave;   // doubles of LDS per wavefront
+    int a_off;      // offset of the staged active row inside the wavefront's LDS slice
+    unsigned* counter;
+};
+
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ int bcast(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+
+__device__ __forceinline__ void wave_sync_lds() {
+    // order this wavefront's LDS writes before its later LDS reads by other lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// N[0..Nw) += neighbour sums over CSR entries [beg, end) of the passive table (p >= 2)
+template <int J>
+__device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
+    const int k = S.k;
+    for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
+        for (int64_t e0 = beg; e0 < end; e0 += kWave) {
+            const int64_t e = e0 + lane;
+            const bool valid = e < end;
+            const int u = valid ? S.col[e] : 0;
+            const int cu = valid ? (int)S.colour[u] : 255;
+            uint64_t rem = __ballot(valid && cu < k && cu != cv);
+            while (rem) {
+                const int first = __ffsll((unsigned long long)rem) - 1;
+                const int c = bcast(cu, first);
+                uint64_t grp = __ballot(cu == c) & rem;
+                rem &= ~grp;
+                double acc[J];
+#pragma unroll
+                for (int t = 0; t < J; ++t) acc[t] = 0.0;
+                while (grp) {
+                    // up to four rows in flight; added in member order
+                    int m[4];
+                    int cnt = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (grp) {
+                            m[q] = __ffsll((unsigned long long)grp) - 1;
+                            grp &= grp - 1;
+                            ++cnt;
+                        } else {
+                            m[q] = m[0];
+                        }
+                    }
+                    double x[4][J];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int uq = bcast(u, m[q]);
+                        const double* row = S.P + (int64_t)uq * S.pstride + c0;
+#pragma unroll
+                        for (int t = 0; t < J; ++t) {
+                            const int j = c0 + lane + kWave * t;
+                            x[q][t] = (q < cnt && j < S.Wp) ? row[lane + kWave * t] : 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q < cnt) {
+#pragma unroll
+                            for (int t = 0; t < J; ++t) acc[t] += x[q][t];
+                        }
+                }
+                const uint16_t* fm = S.fold + ((int64_t)c * k + cv) * S.Wp;
+#pragma unroll
+                for (int t = 0; t < J; ++t) {
+                    const int j = c0 + lane + kWave * t;
+                    if (j < S.Wp) {
+                        const uint16_t idx = fm[j];
+                        if (idx != kNoSlot) N[idx] += acc[t];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// N[lane'] += number of neighbours in [beg, end) with colour c, lane' = c renumbered without cv
+__device__ void count_colours(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
+    const int k = S.k;
+    unsigned cnt = 0;
+    const int my_c = lane + (lane >= cv ? 1 : 0);
+    for (int64_t e0 = beg; e0 < end; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        const bool valid = e < end;
+        const int cu = valid ? (int)S.colour[S.col[e]] : 255;
+        for (int c = 0; c < k; ++c) {
+            const uint64_t b = __ballot(cu == c);
+            if (c == my_c) cnt += (unsigned)__popcll((unsigned long long)b);
+        }
+    }
+    if (lane < k - 1) N[lane] += (double)cnt;
+}
+
+// out row of v from N (LDS) and the active row of v
+__device__ void combine_store(const StepParams& S, int v, double* N, double* Ash, int lane) {
+    double* orow = S.O + (int64_t)v * S.ostride;
+    if (S.a == 1) {
+        // T' is the single vertex v: C(v, T', {col(v)}) = 1, so C(v, T, .) = N(v, .)
+        for (int r = lane; r < S.Ws; r += kWave) orow[r] = N[r];
+        return;
+    }
+    const double* arow = S.A + (int64_t)v * S.astride;
+    for (int r = lane; r < S.Wa; r += kWave) Ash[r] = arow[r];
+    wave_sync_lds();
+    if (S.Ws >= kWave / 2) {
+        for (int r = lane; r < S.Ws; r += kWave) {
+            double sum = 0.0;
+            const uint32_t* sp = S.split + r;
+            for (int j = 0; j < S.npairs; ++j) {
+                const uint32_t pr = sp[(int64_t)j * S.Ws];
+                sum += Ash[pr & 0xFFFFu] * N[pr >> 16];
+            }
+            orow[r] = sum;
+        }
+    } else {
+        // few outputs: G lanes per output set, pairs strided over 64/G parts, fixed-order reduce
+        int G = 1;
+        while (G < S.Ws) G <<= 1;
+        const int parts = kWave / G;
+        const int r = lane & (G - 1);
+        const int part = lane / G;
+        double sum = 0.0;
+        if (r < S.Ws) {
+            const uint32_t* sp = S.split + r;
+            for (int j = part; j < S.npairs; j += parts) {
+                const uint32_t pr = sp[(int64_t)j * S.Ws];
+                sum += Ash[pr & 0xFFFFu] * N[pr >> 16];
+            }
+        }
+        for (int off = G; off < kWave; off <<= 1) sum += __shfl_xor(sum, off);
+        if (part == 0 && r < S.Ws) orow[r] = sum;
+    }
+}
+
+template <int J>
+__global__ __launch_bounds__(256) void k_split(StepParams S) {
+    extern __shared__ double lds[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    double* N = lds + (int64_t)wib * S.lds_wave;
+    double* Ash = N + S.a_off;
+    const int64_t total = S.n_chunks + S.n_light;
+    for (;;) {
+        unsigned it = 0;
+        if (lane == 0) it = atomicAdd(S.counter, 1u);
+        const int64_t item = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)it);
+        if (item >= total) break;
+        int v;
+        int64_t beg, end;
+        const bool is_chunk = item < S.n_chunks;
+        if (is_chunk) {
+            const ChunkItem ch = S.chunks[item];
+            v = ch.v;
+            beg = ch.beg;
+            end = ch.beg + ch.len;
+        } else {
+            v = S.light[item - S.n_chunks];
+            beg = S.row_ptr[v];
+            end = S.row_ptr[v + 1];
+        }
+        v = __builtin_amdgcn_readfirstlane(v);
+        // a vertex without a valid colour (>= k) roots no colourful embedding
+        const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
+        if (!is_chunk && (beg == end || cv >= S.k)) {
+            double* orow = S.O + (int64_t)v * S.ostride;
+            for (int r = lane; r < S.Ws; r += kWave) orow[r] = 0.0;
+            continue;
+        }
+        for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
+        wave_sync_lds();
+        if (cv < S.k) {
+            if (S.p == 1) count_colours(S, beg, end, cv, N, lane);
+            else gather_fold<J>(S, beg, end, cv, N, lane);
+        }
+        wave_sync_lds();
+        if (is_chunk) {
+            double* prow = S.partial + item * S.nstride;
+            for (int r = lane; r < S.Nw; r += kWave) prow[r] = N[r];
+        } else {
+            combine_store(S, v, N, Ash, lane);
+        }
+        wave_sync_lds();
+    }
+}
+
+// rows that were cut: add the chunk partials in chunk order, then combine
+__global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
+    extern __shared__ double lds[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    double* N = lds + (int64_t)wib * S.lds_wave;
+    double* Ash = N + S.a_off;
+    for (;;) {
+        unsigned it = 0;
+        if (lane == 0) it = atomicAdd(S.counter, 1u);
+        const int64_t item = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)it);
+        if (item >= S.n_hubs) break;
+        const HubItem h = S.hubs[item];
+        for (int r = lane; r < S.Nw; r += kWave) {
+            double sum = 0.0;
+            const double* pp = S.partial + h.first_chunk * S.nstride + r;
+            for (int c = 0; c < h.n_chunks; ++c) sum += pp[(int64_t)c * S.nstride];
+            N[r] = sum;
+        }
+        wave_sync_lds();
+        combine_store(S, h.v, N, Ash, lane);
+        wave_sync_lds();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------------------------
+
+__global__ void k_fill_u32(unsigned* p, int64_t n, unsigned v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// colours[b*n + v] = floor(k * h / 2^64), h = mix64(mix64(seed + G*(iter+1)) + H*(v+1))
+__global__ void k_colour(uint64_t seed, uint64_t first_iter, int64_t n, int k, int B, uint8_t* out) {
+    const int64_t total = (int64_t)B * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / n, v = i - b * n;
+        const uint64_t base = mix64(seed + 0x9E3779B97F4A7C15ULL * (first_iter + (uint64_t)b + 1));
+        const uint64_t h = mix64(base + 0xD1B54A32D192ED03ULL * (uint64_t)(v + 1));
+        out[i] = (uint8_t)__umul64hi(h, (uint64_t)k);
+    }
+}
+
+// fixed-order two-level sum of x[0..n) into out[0]; partial has `blocks` slots
+constexpr int kRedThreads = 256;
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_blocks(const double* x, int64_t n, int64_t per_block,
+                                                                double* partial) {
+    __shared__ double sh[kRedThreads];
+    const int64_t lo = blockIdx.x * per_block;
+    const int64_t hi = lo + per_block < n ? lo + per_block : n;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kRedThreads) s += x[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* partial, int blocks, double* out) {
+    __shared__ double sh[kRedThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < blocks; i += kRedThreads) s += partial[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// CSR validation (row offsets already checked on the host): flags bit0 column out of range,
+// bit1 self-loop, bit2 unsorted or duplicate, bit3 asymmetric
+__global__ void k_validate(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, unsigned* flags) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        // row of e: last v with row_ptr[v] <= e
+        int64_t lo = 0, hi = n;  // invariant row_ptr[lo] <= e < row_ptr[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (row_ptr[mid] <= e) lo = mid; else hi = mid;
+        }
+        const int64_t v = lo;
+        const int32_t u = col[e];
+        unsigned f = 0;
+        if (u < 0 || u >= n) f |= 1u;
+        else {
+            if (u == v) f |= 2u;
+            if (e > row_ptr[v] && col[e - 1] >= u) f |= 4u;
+            // v in row u?
+            int64_t a = row_ptr[u], b = row_ptr[u + 1];
+            bool found = false;
+            while (a < b) {
+                const int64_t m = (a + b) / 2;
+                const int32_t w = col[m];
+                if (w == v) { found = true; break; }
+                if (w < v) a = m + 1; else b = m;
+            }
+            if (!found) f |= 8u;
+        }
+        if (f) atomicOr(flags, f);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+
+static inline int grid_for(int64_t n, int threads, int cap) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_colour(uint64_t seed, uint64_t first_iter, int64_t n, int k, int B, uint8_t* out, hipStream_t st) {
+    const int64_t total = (int64_t)B * n;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colour, dim3(grid_for(total, 256, 16384)), dim3(256), 0, st, seed, first_iter, n, k, B, out);
+    return hipGetLastError();
+}
+
+int reduce_blocks_for(int64_t n) {
+    int64_t b = (n + 65535) / 65536;
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* out, hipStream_t st) {
+    const int blocks = reduce_blocks_for(n);
+    const int64_t per = (n + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_reduce_blocks, dim3(blocks), dim3(kRedThreads), 0, st, x, n, per, partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partial, blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, unsigned* flags,
+                           hipStream_t st) {
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, st, row_ptr, col, n, nnz, flags);
+    return hipGetLastError();
+}
+
+// columns per lane per pass of the passive row
+static int pick_J(int Wp) {
+    if (Wp <= 64) return 1;
+    if (Wp <= 128) return 2;
+    if (Wp <= 256) return 4;
+    return 8;
+}
+
+hipError_t launch_split(const StepParamsHost& h, hipStream_t st) {
+    StepParams S;
+    S.row_ptr = h.row_ptr; S.col = h.col; S.colour = h.colour;
+    S.light = h.light; S.chunks = h.chunks; S.hubs = h.hubs;
+    S.n_light = h.n_light; S.n_chunks = h.n_chunks; S.n_hubs = h.n_hubs;
+    S.P = h.P; S.A = h.A; S.O = h.O; S.partial = h.partial;
+    S.fold = h.fold; S.split = h.split;
+    S.pstride = h.pstride; S.astride = h.astride; S.ostride = h.ostride; S.nstride = h.nstride;
+    S.k = h.k; S.s = h.s; S.a = h.a; S.p = h.p;
+    S.Wa = h.Wa; S.Wp = h.Wp; S.Ws = h.Ws; S.Nw = h.Nw; S.npairs = h.npairs;
+    const int n_pad = pad_stride(h.Nw);
+    const int a_pad = (h.a >= 2) ? pad_stride(h.Wa) : 0;
+    S.a_off = n_pad;
+    S.lds_wave = n_pad + a_pad;
+    // up to four wavefronts per workgroup, fewer when one wavefront's slice is large
+    int waves_per_block = 4;
+    while (waves_per_block > 1 && (size_t)S.lds_wave * waves_per_block * sizeof(double) > 64 * 1024)
+        waves_per_block >>= 1;
+    if ((size_t)S.lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
+    const int threads = waves_per_block * kWave;
+    const size_t lds = (size_t)S.lds_wave * waves_per_block * sizeof(double);
+    int J = (h.p >= 2) ? pick_J(h.Wp) : 1;
+    const void* fn = nullptr;
+    switch (J) {
+        case 1: fn = (const void*)k_split<1>; break;
+        case 2: fn = (const void*)k_split<2>; break;
+        case 4: fn = (const void*)k_split<4>; break;
+        default: fn = (const void*)k_split<8>; break;
+    }
+    int per_cu = 0;
+    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    if (err != hipSuccess) return err;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int64_t total = h.n_chunks + h.n_light;
+    int64_t blocks = (int64_t)per_cu * h.n_cu;
+    const int64_t need = (total + waves_per_block - 1) / waves_per_block;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    S.counter = h.counters;
+    if (total > 0) {
+        switch (J) {
+            case 1: hipLaunchKernelGGL(k_split<1>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
+            case 2: hipLaunchKernelGGL(k_split<2>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
+            case 4: hipLaunchKernelGGL(k_split<4>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
+            default: hipLaunchKernelGGL(k_split<8>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
+        }
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (h.n_hubs > 0) {
+        S.counter = h.counters + 1;
+        int per_cu2 = 0;
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_hub_finish, threads, lds);
+        if (err != hipSuccess) return err;
+        if (per_cu2 < 1) return hipErrorInvalidConfiguration;
+        int64_t b2 = (int64_t)per_cu2 * h.n_cu;
+        const int64_t need2 = (h.n_hubs + waves_per_block - 1) / waves_per_block;
+        if (b2 > need2) b2 = need2;
+        hipLaunchKernelGGL(k_hub_finish, dim3((unsigned)b2), dim3(threads), lds, st, S);
+        err = hipGetLastError();
+    }
+    return err;
+}
+
+size_t split_lds_bytes(int Nw, int Wa, int a) {
+    const int n_pad = pad_stride(Nw);
+    const int a_pad = (a >= 2) ? pad_stride(Wa) : 0;
+    return (size_t)(n_pad + a_pad) * sizeof(double);
+}
+
+}  // namespace cc

@@ -1,0 +1,439 @@
+// Template planner (host): rooting, the active/passive partition, table liveness, automorphism
+// count, bookkeeping, and the device constant tables (colour-set split lists and fold maps).
+//
+// Partition (Section 2.1, Figure 1(a); Algorithm 1, "Partition T into subtrees"): the template is
+// rooted at rho; the sub-template at a vertex x with children c_1..c_m is built by attaching the
+// children's full subtrees one at a time. Attaching c_j is one cut of Eq. 1: active part T' = x
+// with c_1..c_{j-1} attached, passive part T'' = the subtree of c_j rooted at c_j. Leaves of the
+// partition are single vertices.
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <numeric>
+
+#include "cc_internal.h"
+
+namespace cc {
+
+int64_t binom(int n, int r) {
+    if (r < 0 || n < 0 || r > n) return 0;
+    int64_t b = 1;
+    for (int i = 1; i <= r; ++i) b = b * (n - r + i) / i;
+    return b;
+}
+
+int pad_stride(int W) {
+    if (W <= 1) return 1;
+    if (W <= 16) {
+        int s = 1;
+        while (s < W) s <<= 1;
+        return s;
+    }
+    return (W + 15) / 16 * 16;
+}
+
+namespace {
+
+// colex rank over K colours: rank({c_0 < c_1 < ...}) = sum_j C(c_j, j+1)
+int colex_rank(uint32_t mask) {
+    int r = 0, j = 0;
+    for (int c = 0; mask; ++c, mask >>= 1)
+        if (mask & 1u) r += (int)binom(c, ++j);
+    return r;
+}
+
+// all masks of popcount m over K bits, in colex (= increasing numeric) order
+std::vector<uint32_t> masks_of(int K, int m) {
+    std::vector<uint32_t> v;
+    for (uint32_t x = 0; x < (1u << K); ++x)
+        if (__builtin_popcount(x) == m) v.push_back(x);
+    return v;
+}
+
+uint32_t expand_bits(uint32_t m, int c) {  // insert a zero bit at position c
+    uint32_t lo = m & ((1u << c) - 1u);
+    return lo | ((m >> c) << (c + 1));
+}
+
+uint32_t compress_bits(uint32_t m, int c) {  // delete bit position c
+    uint32_t lo = m & ((1u << c) - 1u);
+    return lo | ((m >> (c + 1)) << c);
+}
+
+struct Tree {
+    int k;
+    std::vector<std::vector<int>> adj;
+};
+
+bool load_tree(int k, const int32_t* e, Tree* t, std::string* err) {
+    t->k = k;
+    t->adj.assign(k, {});
+    for (int i = 0; i < k - 1; ++i) {
+        int u = e[2 * i], v = e[2 * i + 1];
+        if (u < 0 || v < 0 || u >= k || v >= k || u == v) {
+            *err = "template edge out of range or a self-loop";
+            return false;
+        }
+        if (std::find(t->adj[u].begin(), t->adj[u].end(), v) != t->adj[u].end()) {
+            *err = "duplicate template edge";
+            return false;
+        }
+        t->adj[u].push_back(v);
+        t->adj[v].push_back(u);
+    }
+    std::vector<int> seen(k, 0), st{0};
+    seen[0] = 1;
+    int cnt = 0;
+    while (!st.empty()) {
+        int x = st.back();
+        st.pop_back();
+        ++cnt;
+        for (int y : t->adj[x])
+            if (!seen[y]) { seen[y] = 1; st.push_back(y); }
+    }
+    if (cnt != k) {
+        *err = "template is not connected (k-1 edges must form a tree)";
+        return false;
+    }
+    return true;
+}
+
+std::vector<int> centres(const Tree& t) {
+    int k = t.k;
+    if (k <= 2) {
+        std::vector<int> c;
+        for (int i = 0; i < k; ++i) c.push_back(i);
+        return c;
+    }
+    std::vector<int> deg(k), removed(k, 0), layer;
+    for (int i = 0; i < k; ++i) {
+        deg[i] = (int)t.adj[i].size();
+        if (deg[i] == 1) layer.push_back(i);
+    }
+    int left = k;
+    while (left > 2) {
+        std::vector<int> nxt;
+        for (int x : layer) {
+            removed[x] = 1;
+            --left;
+            for (int y : t.adj[x])
+                if (!removed[y] && --deg[y] == 1) nxt.push_back(y);
+        }
+        layer = nxt;
+    }
+    std::vector<int> c;
+    for (int i = 0; i < k; ++i)
+        if (!removed[i]) c.push_back(i);
+    return c;
+}
+
+// AHU canonical string of the subtree of x (parent p excluded)
+std::string canon(const Tree& t, int x, int p) {
+    std::vector<std::string> ch;
+    for (int y : t.adj[x])
+        if (y != p) ch.push_back(canon(t, y, x));
+    std::sort(ch.begin(), ch.end());
+    std::string s = "(";
+    for (auto& c : ch) s += c;
+    return s + ")";
+}
+
+// automorphisms of the subtree of x that fix x: product over vertices of the factorials of the
+// multiplicities of isomorphic child subtrees
+double rooted_aut(const Tree& t, int x, int p) {
+    double a = 1.0;
+    std::map<std::string, int> mult;
+    for (int y : t.adj[x])
+        if (y != p) {
+            a *= rooted_aut(t, y, x);
+            mult[canon(t, y, x)]++;
+        }
+    for (auto& kv : mult)
+        for (int i = 2; i <= kv.second; ++i) a *= i;
+    return a;
+}
+
+// |Aut(T)|: automorphisms fix the centre (or the centre edge as a set)
+double tree_aut(const Tree& t) {
+    auto c = centres(t);
+    if (c.size() == 1) return rooted_aut(t, c[0], -1);
+    double a = rooted_aut(t, c[0], c[1]) * rooted_aut(t, c[1], c[0]);
+    if (canon(t, c[0], c[1]) == canon(t, c[1], c[0])) a *= 2.0;
+    return a;
+}
+
+struct Rooted {
+    std::vector<int> parent, size;
+    std::vector<std::vector<int>> kids;
+};
+
+Rooted root_at(const Tree& t, int r) {
+    Rooted R;
+    R.parent.assign(t.k, -1);
+    R.size.assign(t.k, 1);
+    R.kids.assign(t.k, {});
+    std::function<int(int, int)> dfs = [&](int x, int p) {
+        R.parent[x] = p;
+        for (int y : t.adj[x])
+            if (y != p) {
+                R.kids[x].push_back(y);
+                R.size[x] += dfs(y, x);
+            }
+        return R.size[x];
+    };
+    dfs(r, -1);
+    return R;
+}
+
+int64_t W_of(int k, int t) { return binom(k - 1, t - 1); }
+
+// combine multiply-adds of attaching children of the given sizes in this order
+int64_t chain_combine(int k, const std::vector<int>& sizes) {
+    int a = 1;
+    int64_t c = 0;
+    for (int p : sizes) {
+        int s = a + p;
+        if (a >= 2) c += W_of(k, s) * binom(s - 1, p);
+        a = s;
+    }
+    return c;
+}
+
+// order the children of every vertex: the cheapest combine (exhaustive up to 7 children),
+// ties broken towards larger subtrees first; `smallest_first` gives the fixed reference order
+void order_children(int k, Rooted* R, bool smallest_first) {
+    for (int x = 0; x < k; ++x) {
+        auto& ch = R->kids[x];
+        std::sort(ch.begin(), ch.end(), [&](int a, int b) {
+            if (R->size[a] != R->size[b])
+                return smallest_first ? R->size[a] < R->size[b] : R->size[a] > R->size[b];
+            return a < b;
+        });
+        if (smallest_first || ch.size() < 2 || ch.size() > 7) continue;
+        std::vector<int> best = ch, perm = ch;
+        auto sizes = [&](const std::vector<int>& o) {
+            std::vector<int> s;
+            for (int y : o) s.push_back(R->size[y]);
+            return s;
+        };
+        int64_t best_c = chain_combine(k, sizes(ch));
+        std::sort(perm.begin(), perm.end());
+        do {
+            int64_t c = chain_combine(k, sizes(perm));
+            if (c < best_c) { best_c = c; best = perm; }
+        } while (std::next_permutation(perm.begin(), perm.end()));
+        ch = best;
+    }
+}
+
+struct Arena {
+    // first-fit allocator over columns
+    std::vector<std::pair<int64_t, int64_t>> used;  // (off, len)
+    int64_t peak = 0;
+    int64_t alloc(int64_t len) {
+        std::sort(used.begin(), used.end());
+        int64_t off = 0;
+        for (auto& u : used) {
+            if (u.first - off >= len) break;
+            off = std::max(off, u.first + u.second);
+        }
+        used.push_back({off, len});
+        peak = std::max(peak, off + len);
+        return off;
+    }
+    void release(int64_t off) {
+        for (size_t i = 0; i < used.size(); ++i)
+            if (used[i].first == off) { used.erase(used.begin() + i); return; }
+    }
+};
+
+struct Schedule {
+    std::vector<Split> splits;
+    std::vector<Table> tables;
+    int64_t arena_cols = 0;
+    int64_t live_peak = 0;
+};
+
+Schedule schedule(int k, const Rooted& R, int root) {
+    Schedule S;
+    Arena A;
+    int64_t live = 0;
+    std::function<int(int)> compute = [&](int x) -> int {
+        int act = -1, a = 1;
+        for (size_t j = 0; j < R.kids[x].size(); ++j) {
+            int c = R.kids[x][j];
+            int pas = compute(c);
+            int p = R.size[c];
+            int s = a + p;
+            bool last_root = (x == root) && (j + 1 == R.kids[x].size());
+            Split sp{};
+            sp.s = s; sp.a = a; sp.p = p; sp.act = act; sp.pas = pas;
+            sp.Wa = (int)W_of(k, a); sp.Wp = (int)W_of(k, p); sp.Ws = (int)W_of(k, s);
+            sp.Nw = (int)binom(k - 1, p);
+            sp.npairs = (int)binom(s - 1, p);
+            if (last_root) {
+                sp.out = -2;
+            } else {
+                Table t{};
+                t.size = s; t.W = sp.Ws; t.stride = pad_stride(t.W);
+                t.col_off = A.alloc(t.stride);
+                live += t.stride;
+                S.tables.push_back(t);
+                sp.out = (int)S.tables.size() - 1;
+            }
+            S.live_peak = std::max(S.live_peak, live);
+            if (act >= 0) { A.release(S.tables[act].col_off); live -= S.tables[act].stride; }
+            if (pas >= 0) { A.release(S.tables[pas].col_off); live -= S.tables[pas].stride; }
+            S.splits.push_back(sp);
+            act = sp.out;
+            a = s;
+        }
+        return act;  // -1 when x is a leaf of T
+    };
+    compute(root);
+    S.arena_cols = A.peak;
+    return S;
+}
+
+}  // namespace
+
+cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_plan* P,
+                     std::string* err) {
+    if (k < 1 || k > kMaxK) {
+        *err = "k must be in [1, 16]";
+        return CC_ERANGE;
+    }
+    if (k > 1 && !edges) {
+        *err = "edges is NULL";
+        return CC_EINVAL;
+    }
+    Tree t;
+    if (!load_tree(k, edges, &t, err)) return CC_EINVAL;
+    if (root < -1 || root >= k) {
+        *err = "root out of range";
+        return CC_EINVAL;
+    }
+    P->k = k;
+    P->edges.assign(edges, edges + 2 * (k - 1));
+    P->aut = tree_aut(t);
+
+    // colour-set-edge units on the reference partition (root = centre with the smallest label)
+    {
+        int c0 = centres(t)[0];
+        Rooted R = root_at(t, c0);
+        int64_t u = 0;
+        for (int x = 0; x < k; ++x)
+            if (x != c0) u += (R.size[x] >= 2) ? binom(k, R.size[x]) : 1;
+        P->units_per_edge = u;
+    }
+
+    const bool reference = (flags & CC_PLAN_CENTRE_SMALLEST) != 0;
+    std::vector<int> candidates;
+    if (root >= 0) candidates.push_back(root);
+    else if (reference) candidates.push_back(centres(t)[0]);
+    else for (int r = 0; r < k; ++r) candidates.push_back(r);
+
+    // choose the root: fewest doubles gathered per edge (weighted 256x: one gathered double per
+    // edge costs about as much HBM time as 256 combine multiply-adds per vertex at average degree
+    // ~30), then the smaller table arena
+    double best_cost = 1e300;
+    Schedule best;
+    Rooted bestR;
+    int best_root = candidates[0];
+    for (int r : candidates) {
+        Rooted R = root_at(t, r);
+        order_children(k, &R, reference);
+        Schedule S = schedule(k, R, r);
+        int64_t g = 0, c = 0;
+        for (auto& sp : S.splits) {
+            if (sp.p >= 2) g += sp.Wp;
+            if (sp.a >= 2) c += (int64_t)sp.Ws * sp.npairs;
+        }
+        double cost = 256.0 * (double)g + (double)c + 1e-6 * (double)S.arena_cols;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = S;
+            bestR = R;
+            best_root = r;
+        }
+    }
+    P->root = best_root;
+    P->splits = best.splits;
+    P->tables = best.tables;
+    P->arena_cols = best.arena_cols;
+    P->peak_live_cols = best.live_peak;
+
+    // bookkeeping
+    P->t3_memory = P->t3_compute = P->gather_per_edge = P->combine_per_vertex = 0;
+    P->max_Nw = 0;
+    for (auto& sp : P->splits) {
+        if (sp.out != -2) {
+            P->t3_memory += binom(k, sp.s);
+            P->t3_compute += binom(k, sp.s) * binom(sp.s, sp.a);
+        }
+        if (sp.p >= 2) P->gather_per_edge += sp.Wp;
+        if (sp.a >= 2) P->combine_per_vertex += (int64_t)sp.Ws * sp.npairs;
+        P->max_Nw = std::max(P->max_Nw, sp.Nw);
+    }
+    P->max_stride_N = pad_stride(P->max_Nw);
+
+    // device constants
+    const int K = k - 1;
+    std::vector<uint8_t>& C = P->consts;
+    C.clear();
+    auto align = [&]() { while (C.size() % 256) C.push_back(0); };
+    for (auto& sp : P->splits) {
+        sp.split_off = -1;
+        sp.fold_off = -1;
+        if (sp.a >= 2) {
+            // for every output set R (|R| = s-1, colex order) its p-subsets Q in increasing
+            // numeric order: (rank(R \ Q), rank(Q)) packed as lo16 | hi16 << 16, layout [j][r]
+            align();
+            sp.split_off = (int64_t)C.size();
+            auto outs = masks_of(K, sp.s - 1);
+            std::vector<uint32_t> tab((size_t)sp.npairs * outs.size());
+            for (size_t r = 0; r < outs.size(); ++r) {
+                uint32_t R = outs[r];
+                int j = 0;
+                uint32_t q = 0;
+                do {  // sub-masks of R in increasing numeric order
+                    if (__builtin_popcount(q) == sp.p) {
+                        uint32_t ia = (uint32_t)colex_rank(R & ~q), in = (uint32_t)colex_rank(q);
+                        tab[(size_t)j * outs.size() + r] = ia | (in << 16);
+                        ++j;
+                    }
+                    q = (q - R) & R;
+                } while (q != 0);
+            }
+            const uint8_t* b = reinterpret_cast<const uint8_t*>(tab.data());
+            C.insert(C.end(), b, b + tab.size() * 4);
+        }
+        if (sp.p >= 2) {
+            // fold map M[cu][cv][j]: passive entry j of a neighbour u (colour cu) is the set
+            // R_u (|R_u| = p-1) over the colours other than cu; it adds to N(v, Q) with
+            // Q = R_u + {cu} written over the colours other than cv, unless cv is in R_u
+            align();
+            sp.fold_off = (int64_t)C.size();
+            auto rows = masks_of(K, sp.p - 1);
+            std::vector<uint16_t> tab((size_t)k * k * rows.size(), kNoSlot);
+            for (int cu = 0; cu < k; ++cu)
+                for (int cv = 0; cv < k; ++cv) {
+                    if (cu == cv) continue;
+                    for (size_t j = 0; j < rows.size(); ++j) {
+                        uint32_t full = expand_bits(rows[j], cu);
+                        if (full >> cv & 1u) continue;
+                        uint32_t Q = compress_bits(full | (1u << cu), cv);
+                        tab[((size_t)cu * k + cv) * rows.size() + j] = (uint16_t)colex_rank(Q);
+                    }
+                }
+            const uint8_t* b = reinterpret_cast<const uint8_t*>(tab.data());
+            C.insert(C.end(), b, b + tab.size() * 2);
+        }
+    }
+    align();
+    if (C.empty()) C.resize(256, 0);
+    return CC_OK;
+}
+
+}  // namespace cc

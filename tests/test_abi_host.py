@@ -1,0 +1,142 @@
+"""Host-side checks of libcc.so without a GPU: exported symbols, planner logic, error paths.
+
+Nothing here launches a kernel; cc_plan_create / cc_plan_info_get / cc_estimate are host-only.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+import paper_1804_09764_amd as cc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "cc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cc_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = cc.lib()
+    names = _declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(cc.EXPORTS) == names
+
+
+def test_plan_rejects_bad_templates():
+    """k = 1 is accepted; non-trees, k > 16, duplicate edges and bad roots are rejected."""
+    p = cc.Plan(np.zeros((0, 2)), bind=False)
+    assert p.info.k == 1 and p.info.n_splits == 0
+    with pytest.raises(cc.CCError) as e:
+        cc.Plan([[0, 1], [1, 2], [2, 0]], bind=False)  # k=4: a triangle plus an isolated vertex
+    assert e.value.status == -1
+    with pytest.raises(cc.CCError) as e:
+        cc.Plan(inputs.path_tree(17), bind=False)
+    assert e.value.status == -2
+    with pytest.raises(cc.CCError):
+        cc.Plan([[0, 1], [0, 1]], bind=False)
+    with pytest.raises(cc.CCError):
+        cc.Plan(inputs.path_tree(4), root=4, bind=False)
+
+
+@pytest.mark.parametrize("k", range(1, 11))
+def test_aut_matches_oracle(k):
+    for T in inputs.all_trees(k):
+        assert cc.Plan(T, bind=False).info.aut == oracle.aut(T)
+
+
+@pytest.mark.parametrize("k", [12, 13, 14, 15, 16])
+def test_aut_large_random_trees(k):
+    for seed in range(3):
+        T = inputs.pruefer_tree(k, seed)
+        assert cc.Plan(T, bind=False).info.aut == oracle.aut(T)
+    assert cc.Plan(inputs.star_tree(k), bind=False).info.aut == math.factorial(k - 1)
+
+
+@pytest.mark.parametrize("k", range(2, 17))
+def test_partition_invariants(k):
+    for seed in range(5):
+        T = inputs.pruefer_tree(k, seed)
+        for root in (-1, 0, k - 1):
+            p = cc.Plan(T, root=root, bind=False)
+            assert p.info.n_splits == k - 1
+            assert p.splits[-1][0] == k
+            for s, a, pp in p.splits:
+                assert s == a + pp and a >= 1 and pp >= 1
+            # the passive sizes are the subtree sizes of the non-root vertices
+            assert sorted(pp for _, _, pp in p.splits) == sorted(_subtree_sizes(T, p.info.root))
+
+
+def _subtree_sizes(T, root):
+    k = len(T) + 1
+    adj = [[] for _ in range(k)]
+    for u, v in T:
+        adj[u].append(v)
+        adj[v].append(u)
+    sizes = []
+
+    def dfs(x, par):
+        s = 1
+        for y in adj[x]:
+            if y != par:
+                s += dfs(y, x)
+        if par >= 0:
+            sizes.append(s)
+        return s
+
+    dfs(root, -1)
+    return sizes
+
+
+def test_table3_bookkeeping():
+    """The paper's Table 3: u3-1 = (3, 6), u5-2 = (25, 70), u12-1 = (4082, 24552) are reproduced by
+    end-rooted paths, counting every split sub-template except T itself."""
+    for k, want in [(3, (3, 6)), (5, (25, 70)), (12, (4082, 24552))]:
+        p = cc.Plan(inputs.path_tree(k), root=0, bind=False)
+        assert (p.info.table3_memory, p.info.table3_compute) == want
+
+
+def test_units_reference_partition():
+    # the 5-path rooted at its centre: passive subtrees 2, 1, 2, 1 -> C(5,2)+1+C(5,2)+1 = 22
+    assert cc.Plan(inputs.path_tree(5), bind=False).info.units_per_edge == 22
+    # a star with k-1 leaves: k-1 passive single vertices
+    assert cc.Plan(inputs.star_tree(9), bind=False).info.units_per_edge == 8
+    # the 12-path end-rooted plan still reports units of the centre-rooted reference partition
+    a = cc.Plan(inputs.path_tree(12), root=0, bind=False).info.units_per_edge
+    b = cc.Plan(inputs.path_tree(12), bind=False).info.units_per_edge
+    assert a == b
+
+
+def test_estimate_host():
+    T = inputs.pruefer_tree(6, 3)
+    p = cc.Plan(T, bind=False)
+    X = [10.0, 20.0, 30.0, 40.0]
+    est, se = cc.estimate(p, X)
+    f = 6 ** 6 / math.factorial(6) / p.info.aut
+    assert math.isclose(est, 25.0 * f, rel_tol=1e-15)
+    assert math.isclose(se, np.std(X, ddof=1) / 2 * f, rel_tol=1e-12)
+    assert math.isclose(est, oracle.estimate(6, int(p.info.aut), X), rel_tol=1e-15)
+    mom = cc.estimate_median_of_means(p, [1.0, 3.0, 10.0, 10.0, 100.0, 200.0], 3)
+    assert math.isclose(mom, 10.0 * f, rel_tol=1e-15)
+    with pytest.raises(cc.CCError):
+        cc.estimate_median_of_means(p, [1.0, 2.0, 3.0], 2)
+
+
+def test_no_cpu_fallback_in_product():
+    """The product package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_1804_09764_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt
+                assert "liboracle" not in txt
