@@ -1,0 +1,328 @@
+#!/usr/bin/env python3
+"""Throughput of the colour-coding hot path on one MI355X, in colour-set-edge updates per second.
+
+One step = one pass of the whole hot path over one batch of synthetic input: colour the graph
+B times (B = the workload's colourings per batch), then run the full dynamic program for every
+colouring (all template splits: neighbour gather + combine, cut-row finish, root sum).
+
+Units (CSEU): for a split whose passive sub-template has p vertices, every directed CSR entry
+accounts for C(k, p) colour-set updates (1 when p = 1), summed over the splits of the template's
+reference partition (root at the centre). units per step = nnz * units_per_edge * B.
+
+Usage:
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+  python bench.py --summarize-pmc DIR ...   (turn rocprofv3 --pmc output into profiles/*.json)
+
+Prints one JSON line (rank 0). Only one GPU is used: --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "colour-set·edge updates/s (u12, RMAT-23) plain vs batched; p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1804_09764_amd", "csrc", "cc_kernels.hip")
+
+WORKLOADS = {
+    # R-MAT (a, b, c) = (0.57, 0.19, 0.19), symmetrised, de-duplicated; 12-vertex Pruefer tree
+    "rmat20-ef16-u12": dict(scale=20, ef=16, gseed=1, k=12, tseed=12, B=1, trust=False),
+    "rmat23-ef256-u12": dict(scale=23, ef=256, gseed=3, k=12, tseed=12, B=4, trust=True),
+    "rmat20-ef16-u15": dict(scale=20, ef=16, gseed=1, k=15, tseed=15, B=1, trust=False),
+}
+DEFAULT_WORKLOAD = "rmat20-ef16-u12"
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def widths(k, s, a, p):
+    W = lambda t: math.comb(k - 1, t - 1)  # noqa: E731  colour-anchored row width
+    return W(p), W(a), W(s)
+
+
+def split_bytes(k, s, a, p, n, nnz):
+    """Compulsory HBM bytes of one split's gather+combine launch: every array crosses HBM once.
+
+    CSR columns (4 B per entry) and row offsets (8 B per vertex), colours (1 B per vertex), the
+    passive table when p >= 2 (8 B per vertex per column), the active table when a >= 2, and the
+    output table, all in the colour-anchored widths.
+    """
+    Wp, Wa, Ws = widths(k, s, a, p)
+    b = 4 * nnz + 8 * (n + 1) + n
+    if p >= 2:
+        b += 8 * n * Wp
+    if a >= 2:
+        b += 8 * n * Wa
+    b += 8 * n * Ws
+    return b
+
+
+def loaded_bytes(k, s, a, p, n, nnz):
+    """Bytes the wavefronts request (cache hits included): one passive row per CSR entry whose
+    neighbour colour differs from the row's (expected fraction (k-1)/k), plus the compulsory rest."""
+    Wp, Wa, Ws = widths(k, s, a, p)
+    b = 5 * nnz + 8 * (n + 1) + n + 8 * n * Ws + (8 * n * Wa if a >= 2 else 0)
+    if p >= 2:
+        b += 8 * Wp * nnz * (k - 1) / k
+    return b
+
+
+def load_traffic(workload: str, split_index: int):
+    """HBM traffic per launch (GB) of the dominant kernel from committed rocprofv3 counters, or None
+    if they were taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_split_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_hash") != kernel_hash() or d.get("split_index") != split_index:
+        return None
+    return d["traffic_bytes_per_launch"] / 1e9
+
+
+def cpu_baseline(row_ptr, col, T, target_s=15.0):
+    """The oracle, timed on a bounded sample of the same workload.
+
+    For every split of the reference partition, oracle.step (Eq. 1 as written: per vertex, per
+    colour set, neighbours then splits) runs over a uniform random sample of centre vertices with
+    random integer input tables; CSEU are counted exactly as on the GPU (deg(v) * w(p) per sampled
+    vertex). The sample size is doubled until the sample takes about `target_s` seconds.
+    """
+    import numpy as np
+
+    import oracle
+    import paper_1804_09764_amd as cc
+
+    ref = cc.Plan(T, flags=cc.CC_PLAN_CENTRE_SMALLEST, bind=False)
+    k = ref.k
+    n = len(row_ptr) - 1
+    rng = np.random.default_rng(2024)
+    deg = np.diff(row_ptr)
+
+    def run(m):
+        vs = np.sort(rng.choice(n, size=m, replace=False))
+        starts = row_ptr[vs]
+        lens = deg[vs]
+        nbr_ptr = np.zeros(m + 1, dtype=np.int64)
+        nbr_ptr[1:] = np.cumsum(lens)
+        idx = np.concatenate([col[s:s + l] for s, l in zip(starts, lens)]) if m else np.zeros(0, np.int32)
+        uniq, inv = np.unique(idx, return_inverse=True)
+        units = 0
+        secs = 0.0
+        for (s, a, p) in ref.splits:
+            act = rng.integers(0, 4, size=(m, math.comb(k, a))).astype(np.float64)
+            pas = rng.integers(0, 4, size=(len(uniq), math.comb(k, p))).astype(np.float64)
+            t0 = time.perf_counter()
+            oracle.step(k, s, a, nbr_ptr, inv.astype(np.int32), act, pas)
+            secs += time.perf_counter() - t0
+            units += int(lens.sum()) * (math.comb(k, p) if p >= 2 else 1)
+        return units, secs, m
+
+    m = 64
+    units, secs, m = run(m)
+    while secs < target_s / 2 and m < n:
+        m = min(n, int(m * max(2.0, min(8.0, target_s / max(secs, 1e-3)))))
+        units, secs, m = run(m)
+    return {"value": units / secs, "unit": "CSEU/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{m} uniformly sampled centre vertices, every split of the reference partition, "
+                      f"random integer tables; {units:.3e} CSEU in {secs:.1f} s"}
+
+
+def bench(args):
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1804_09764_amd as cc
+
+    W = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    row_ptr, col = inputs.rmat_graph(W["scale"], W["ef"], W["gseed"], threads=args.gen_threads)
+    n, nnz = len(row_ptr) - 1, len(col)
+    print(f"[bench] graph scale={W['scale']} ef={W['ef']} n={n} nnz={nnz} built in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    T = inputs.pruefer_tree(W["k"], W["tseed"])
+    k, B = W["k"], W["B"]
+    rp_d = torch.from_numpy(row_ptr).to(dev)
+    col_d = torch.from_numpy(col).to(dev)
+    G = cc.Graph(rp_d, col_d, hub_threshold=args.hub_threshold, chunk=args.chunk, trust=W["trust"])
+    P = cc.Plan(T)
+    units_per_edge = P.info.units_per_edge
+    ws = cc.Workspace()
+    colours = torch.empty((B, n), dtype=torch.uint8, device=dev)
+    X = torch.empty(B, dtype=torch.float64, device=dev)
+    ws_bytes = cc.count_workspace_bytes(P, G)
+    print(f"[bench] plan root={P.info.root} splits={P.splits} workspace={ws_bytes / 1e9:.2f} GB "
+          f"graph={G.info}", file=sys.stderr, flush=True)
+
+    def step(i):
+        cc.colour(G, k, seed=args.seed, first_iter=i * B, B=B, out=colours)
+        cc.count(P, G, colours, workspace=ws, out=X)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    P.profile(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    gather_ms, finish_ms, launches = P.profile_read()
+    P.profile(False)
+    Xh = X.cpu().numpy()
+
+    units = float(nnz) * units_per_edge * B * args.steps
+    value = units / elapsed
+    dom = int(np.argmax(gather_ms))
+    s, a, p = P.splits[dom]
+    avg_ms = gather_ms[dom] / max(1, launches[dom])
+    alg = split_bytes(k, s, a, p, n, nnz)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, dom)
+    per_split = [{"s": S, "a": A, "p": Pp, "gather_ms": round(float(g) / max(1, c), 4),
+                  "finish_ms": round(float(f) / max(1, c), 4)}
+                 for (S, A, Pp), g, f, c in zip(P.splits, gather_ms, finish_ms, launches)]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "CSEU/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": f"R-MAT scale {W['scale']} edge factor {W['ef']} "
+                   f"(a,b,c)=(0.57,0.19,0.19) seed {W['gseed']}", "n": n, "nnz": nnz,
+                   "template": f"Pruefer tree k={k} seed {W['tseed']}", "colourings_per_step": B,
+                   "units_per_edge": units_per_edge, "path": "plain"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic,
+                     "kernel": f"k_split split {dom} (s={s}, a={a}, p={p})",
+                     "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": alg,
+                     "loaded_GBps": loaded_bytes(k, s, a, p, n, nnz) / (avg_ms * 1e-3) / 1e9},
+        "splits": per_split,
+        "X_last": [float(x) for x in Xh],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(row_ptr, col, T, target_s=args.cpu_seconds)
+    return out
+
+
+def summarize_pmc(args):
+    """rocprofv3 --pmc output (counter_collection.csv of a FETCH_SIZE run and of a WRITE_SIZE run)
+    -> profiles/k_split_<workload>_pmc.json: the dominant split kernel's bytes per launch, scaled
+    by what the same counters read for a plain copy of known size."""
+    def rows(d):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def per_kernel(rs, counter):
+        d = {}
+        for r in rs:
+            if r.get("Counter_Name") != counter:
+                continue
+            d.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return d
+
+    fetch = per_kernel(rows(args.fetch_dir), "FETCH_SIZE")
+    write = per_kernel(rows(args.write_dir), "WRITE_SIZE")
+    copy_bytes = args.copy_bytes
+
+    def copy_kib(d):
+        cands = [v for name, v in d.items() if "copy" in name.lower() or "elementwise" in name.lower()]
+        vals = [max(v) for v in cands] if cands else []
+        return max(vals) if vals else None
+
+    fk, wk = copy_kib(fetch), copy_kib(write)
+    f_factor = copy_bytes / (fk * 1024.0) if fk else 1.0
+    w_factor = copy_bytes / (wk * 1024.0) if wk else 1.0
+    # dispatches of the split kernel in launch order; the dominant split index picks one per colouring
+    fsplit = [v for name, vs in fetch.items() if "k_split" in name for v in vs]
+    wsplit = [v for name, vs in write.items() if "k_split" in name for v in vs]
+    nspl = args.n_splits
+    idx = args.split_index
+    fsel = [fsplit[i] for i in range(idx, len(fsplit), nspl)]
+    wsel = [wsplit[i] for i in range(idx, len(wsplit), nspl)]
+    fetch_kib = sum(fsel) / len(fsel)
+    write_kib = sum(wsel) / len(wsel)
+    res = {"workload": args.workload, "kernel_hash": kernel_hash(), "split_index": idx,
+           "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
+           "copy_fetch_factor": f_factor, "copy_write_factor": w_factor,
+           "traffic_bytes_per_launch": fetch_kib * 1024.0 * f_factor + write_kib * 1024.0 * w_factor,
+           "command": args.command}
+    path = os.path.join(ROOT, "profiles", f"k_split_{args.workload}_pmc.json")
+    json.dump(res, open(path, "w"), indent=1)
+    print(json.dumps(res))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=777)
+    ap.add_argument("--hub-threshold", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--gen-threads", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--summarize-pmc", action="store_true")
+    ap.add_argument("--fetch-dir")
+    ap.add_argument("--write-dir")
+    ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    ap.add_argument("--split-index", type=int, default=0)
+    ap.add_argument("--n-splits", type=int, default=11)
+    ap.add_argument("--command", default="")
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args)
+        return 0
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the counting path does not span GPUs "
+              "(sharding by colouring or by colour-set column is described in DESIGN.md).",
+              file=sys.stderr)
+        return 2
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    out = bench(args)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

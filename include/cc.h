@@ -122,6 +122,7 @@ typedef struct cc_graph cc_graph;
 typedef struct {
     int32_t hub_threshold;  /* rows with more neighbours than this are cut into chunks (0 = auto) */
     int32_t chunk;          /* neighbours per chunk of a cut row (0 = auto; multiple of 64) */
+    int32_t cols_per_lane;  /* passive-row doubles each lane holds per pass: 1, 2, 4 or 8 (0 = auto) */
 } cc_tuning;
 
 /* flags for cc_graph_prepare */
@@ -146,7 +147,7 @@ typedef struct {
     int64_t n, nnz;
     int64_t max_degree;
     int64_t n_light, n_hubs, n_chunks;
-    int32_t hub_threshold, chunk;
+    int32_t hub_threshold, chunk, cols_per_lane;
 } cc_graph_info;
 
 cc_status cc_graph_info_get(const cc_graph* g, cc_graph_info* out);
@@ -183,6 +184,26 @@ cc_status cc_count_workspace_bytes(const cc_plan* plan, const cc_graph* g, size_
  */
 cc_status cc_count(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
                    void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Measurement                                                                                  */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * Per-split kernel timing. While enabled on a plan, every cc_count with that plan records HIP
+ * events on its stream around (1) the neighbour-gather + combine kernel and (2) the cut-row finish
+ * kernel of each split, for every colouring. Not thread-safe: one counting stream per plan while
+ * enabled. Enabling again clears what was recorded.
+ */
+cc_status cc_profile_enable(cc_plan* plan, int32_t enable);
+
+/*
+ * Synchronise on the recorded events and return, for each of the first n splits (execution
+ * order), the summed milliseconds of its gather kernel and of its finish kernel and the number of
+ * colourings recorded. Any array may be NULL. Recording stays enabled and is cleared.
+ */
+cc_status cc_profile_read(cc_plan* plan, int32_t n, double* gather_ms_host, double* finish_ms_host,
+                          int64_t* launches_host);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Estimate (Algorithm 1, Eq. 3 and the final averaging; Section 2.1 colourful probability)    */

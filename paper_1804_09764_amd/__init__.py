@@ -48,17 +48,19 @@ class _PlanInfo(ctypes.Structure):
 class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("n_light", ctypes.c_int64), ("n_hubs", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
-                ("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+                ("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("cols_per_lane", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+    _fields_ = [("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("cols_per_lane", ctypes.c_int32)]
 
 
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
            "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
-           "cc_estimate", "cc_estimate_median_of_means"]
+           "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read"]
 
 
 @lru_cache(maxsize=1)
@@ -88,6 +90,8 @@ def lib() -> ctypes.CDLL:
         "cc_estimate": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
         "cc_estimate_median_of_means": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ctypes.c_double)]),
+        "cc_profile_enable": (ctypes.c_int, [P, I32]),
+        "cc_profile_read": (ctypes.c_int, [P, I32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -169,6 +173,20 @@ class Plan:
     def handle(self):
         return self._h
 
+    def profile(self, enable: bool = True):
+        """Record per-split kernel times of later counts with this plan (HIP events)."""
+        _check(lib().cc_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(gather_ms[n_splits], finish_ms[n_splits], colourings[n_splits]) recorded so far."""
+        n = self.info.n_splits
+        g = np.zeros(n, dtype=np.float64)
+        f = np.zeros(n, dtype=np.float64)
+        c = np.zeros(n, dtype=np.int64)
+        _check(lib().cc_profile_read(self._h, n, g.ctypes.data if n else None, f.ctypes.data if n else None,
+                                     c.ctypes.data if n else None))
+        return g, f, c
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -183,14 +201,14 @@ class Graph:
     """A CSR graph resident on the GPU (int64 row_ptr, int32 col) with its prepared work lists."""
 
     def __init__(self, row_ptr, col, hub_threshold: int = 0, chunk: int = 0, trust: bool = False,
-                 stream=None):
+                 cols_per_lane: int = 0, stream=None):
         import torch
         self.row_ptr = row_ptr
         self.col = col
         n = row_ptr.numel() - 1
         nnz = col.numel()
         self.n, self.nnz = n, nnz
-        tun = _Tuning(hub_threshold, chunk)
+        tun = _Tuning(hub_threshold, chunk, cols_per_lane)
         nb = ctypes.c_size_t()
         _check(lib().cc_graph_workspace_bytes(n, nnz, ctypes.byref(tun), ctypes.byref(nb)))
         self._ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=row_ptr.device)

@@ -30,18 +30,21 @@ inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 inline int64_t pad32(int64_t n) { return (n + 31) / 32 * 32; }
 
-void resolve_tuning(int64_t nnz, const cc_tuning* t, int32_t* thr, int32_t* chunk) {
+void resolve_tuning(int64_t nnz, const cc_tuning* t, int32_t* thr, int32_t* chunk, int32_t* cols = nullptr) {
     int32_t c = (t && t->chunk > 0) ? t->chunk : (nnz >= ((int64_t)1 << 28) ? 2048 : 512);
     c = (c + 63) / 64 * 64;
     int32_t h = (t && t->hub_threshold > 0) ? t->hub_threshold : 2 * c;
     if (h < c) h = c;
     *thr = h;
     *chunk = c;
+    if (cols) *cols = t ? t->cols_per_lane : 0;
 }
 
 struct GraphLayout {
-    size_t flags_off, light_off, chunk_off, hub_off, total;
+    size_t flags_off, light_off, range_off, chunk_off, hub_off, total;
 };
+
+constexpr int kRangeRows = 64;  // at most this many light rows per range task
 
 GraphLayout graph_layout(int64_t n, int64_t nnz, int32_t thr, int32_t chunk) {
     GraphLayout L;
@@ -49,14 +52,15 @@ GraphLayout graph_layout(int64_t n, int64_t nnz, int32_t thr, int32_t chunk) {
     const int64_t max_chunks = nnz / chunk + max_hubs;
     L.flags_off = 0;
     L.light_off = 256;
-    L.chunk_off = align256(L.light_off + (size_t)n * sizeof(int32_t));
+    L.range_off = align256(L.light_off + (size_t)n * sizeof(int32_t));
+    L.chunk_off = align256(L.range_off + (size_t)(n + 1) * sizeof(int32_t));
     L.hub_off = align256(L.chunk_off + (size_t)max_chunks * sizeof(cc::ChunkItem));
     L.total = align256(L.hub_off + (size_t)max_hubs * sizeof(cc::HubItem));
     return L;
 }
 
 struct CountLayout {
-    size_t arena_off, partial_off, root_off, red_off, ctr_off, total;
+    size_t arena_off, partial_off, root_off, red_off, total;
     int64_t n_pad;
 };
 
@@ -67,8 +71,7 @@ CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
     L.partial_off = align256((size_t)P->arena_cols * (size_t)L.n_pad * sizeof(double));
     L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)P->max_stride_N * sizeof(double));
     L.red_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * sizeof(double));
-    L.ctr_off = align256(L.red_off + 1024 * sizeof(double));
-    L.total = align256(L.ctr_off + (2 * P->splits.size() + 2) * sizeof(unsigned));
+    L.total = align256(L.red_off + 1024 * sizeof(double));
     return L;
 }
 
@@ -143,6 +146,54 @@ cc_status cc_plan_bind_device(cc_plan* P, void* dev, size_t bytes, void* stream)
 
 void cc_plan_destroy(cc_plan* P) { delete P; }
 
+cc_status cc_profile_enable(cc_plan* P, int32_t enable) {
+    if (!P) return fail(CC_EINVAL, "NULL plan");
+    for (auto& v : P->prof_events)
+        for (void* e : v) (void)hipEventDestroy((hipEvent_t)e);
+    P->prof_events.assign(P->splits.size(), {});
+    P->prof_launches.assign(P->splits.size(), 0);
+    P->profiling = enable != 0;
+    return CC_OK;
+}
+
+cc_status cc_profile_read(cc_plan* P, int32_t n, double* gather_ms, double* finish_ms, int64_t* launches) {
+    if (!P) return fail(CC_EINVAL, "NULL plan");
+    if (n < 0 || n > (int32_t)P->splits.size()) return fail(CC_ERANGE, "n out of range");
+    if (P->prof_events.size() != P->splits.size()) {
+        P->prof_events.assign(P->splits.size(), {});
+        P->prof_launches.assign(P->splits.size(), 0);
+    }
+    cc_status st = CC_OK;
+    for (int32_t i = 0; i < (int32_t)P->splits.size(); ++i) {
+        double g = 0.0, f = 0.0;
+        auto& ev = P->prof_events[(size_t)i];
+        for (size_t j = 0; j + 3 <= ev.size(); j += 3) {
+            hipEvent_t a = (hipEvent_t)ev[j], b = (hipEvent_t)ev[j + 1], c = (hipEvent_t)ev[j + 2];
+            float t1 = 0.f, t2 = 0.f;
+            hipError_t e = hipEventSynchronize(c);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t1, a, b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t2, b, c);
+            if (e != hipSuccess) st = hip_fail(e, "profile events");
+            g += t1;
+            f += t2;
+        }
+        if (i < n) {
+            if (gather_ms) gather_ms[i] = g;
+            if (finish_ms) finish_ms[i] = f;
+            if (launches) launches[i] = P->prof_launches[(size_t)i];
+        }
+        for (void* e : ev) (void)hipEventDestroy((hipEvent_t)e);
+        ev.clear();
+        P->prof_launches[(size_t)i] = 0;
+    }
+    return st;
+}
+
+cc_plan::~cc_plan() {
+    for (auto& v : prof_events)
+        for (void* e : v) (void)hipEventDestroy((hipEvent_t)e);
+}
+
 cc_status cc_graph_workspace_bytes(int64_t n, int64_t nnz, const cc_tuning* tuning, size_t* bytes) {
     if (!bytes || n < 0 || nnz < 0) return fail(CC_EINVAL, "bad argument");
     if (n >= ((int64_t)1 << 31)) return fail(CC_ERANGE, "n must be below 2^31");
@@ -160,8 +211,10 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     if (n < 0 || nnz < 0 || !row_ptr_dev || (nnz > 0 && !col_dev) || !ws_dev)
         return fail(CC_EINVAL, "bad graph arguments");
     if (n >= ((int64_t)1 << 31)) return fail(CC_ERANGE, "n must be below 2^31");
-    int32_t thr, chunk;
-    resolve_tuning(nnz, tuning, &thr, &chunk);
+    int32_t thr, chunk, cols;
+    resolve_tuning(nnz, tuning, &thr, &chunk, &cols);
+    if (cols != 0 && cols != 1 && cols != 2 && cols != 4 && cols != 8)
+        return fail(CC_EINVAL, "cols_per_lane must be 0, 1, 2, 4 or 8");
     GraphLayout L = graph_layout(n, nnz, thr, chunk);
     if (ws_bytes < L.total) return fail(CC_ENOSPC, "graph workspace too small");
     hipStream_t st = (hipStream_t)stream;
@@ -224,7 +277,24 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     std::stable_sort(light.begin(), light.end(), [&](int32_t a, int32_t b) {
         return (rp[a + 1] - rp[a]) > (rp[b + 1] - rp[b]);
     });
-    // chunk items interleaved across cut rows is unnecessary: each chunk is bounded by `chunk`
+    // light ranges: consecutive light rows (heaviest first) totalling at most `chunk` entries
+    // (a single heavier row forms its own range) and at most kRangeRows rows
+    std::vector<int32_t> starts;
+    starts.reserve(light.size() / 8 + 2);
+    {
+        int64_t acc = 0, cnt = 0;
+        for (size_t i = 0; i < light.size(); ++i) {
+            const int64_t d = rp[light[i] + 1] - rp[light[i]];
+            if (cnt == 0 || acc + d > chunk || cnt == kRangeRows) {
+                starts.push_back((int32_t)i);
+                acc = 0;
+                cnt = 0;
+            }
+            acc += d;
+            ++cnt;
+        }
+        starts.push_back((int32_t)light.size());
+    }
     cc_graph* G = new (std::nothrow) cc_graph();
     if (!G) return fail(CC_ENOMEM, "graph allocation failed");
     G->n = n;
@@ -233,6 +303,8 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     G->row_ptr = row_ptr_dev;
     G->col = col_dev;
     G->light = (int32_t*)(ws + L.light_off);
+    G->light_start = (int32_t*)(ws + L.range_off);
+    G->n_ranges = (int64_t)starts.size() - 1;
     G->chunks = (cc::ChunkItem*)(ws + L.chunk_off);
     G->hubs = (cc::HubItem*)(ws + L.hub_off);
     G->n_light = (int64_t)light.size();
@@ -240,14 +312,13 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     G->n_hubs = (int64_t)hubs.size();
     G->hub_threshold = thr;
     G->chunk = chunk;
-    if (G->n_light + G->n_chunks >= ((int64_t)1 << 32)) {
-        delete G;
-        return fail(CC_ERANGE, "too many work items");
-    }
+    G->cols_per_lane = cols;
     e = hipGetDevice(&G->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&G->n_cu, hipDeviceAttributeMultiprocessorCount, G->device);
     if (e == hipSuccess && !light.empty())
         e = hipMemcpyAsync(G->light, light.data(), light.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(G->light_start, starts.data(), starts.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !chunks.empty())
         e = hipMemcpyAsync(G->chunks, chunks.data(), chunks.size() * sizeof(cc::ChunkItem), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !hubs.empty())
@@ -271,6 +342,7 @@ cc_status cc_graph_info_get(const cc_graph* G, cc_graph_info* o) {
     o->n_chunks = G->n_chunks;
     o->hub_threshold = G->hub_threshold;
     o->chunk = G->chunk;
+    o->cols_per_lane = G->cols_per_lane;
     return CC_OK;
 }
 
@@ -306,7 +378,6 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
     double* arena = (double*)(ws + L.arena_off);
     double* partial = (double*)(ws + L.partial_off);
     double* red = (double*)(ws + L.red_off);
-    unsigned* ctr = (unsigned*)(ws + L.ctr_off);
     const int64_t n = G->n;
     const uint8_t* cdev = (const uint8_t*)P->dev;
     hipError_t e = hipSuccess;
@@ -322,7 +393,6 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
             // k = 1: every vertex roots exactly one map
             e = cc::launch_fill_f64(root_out, n, 1.0, st);
         } else {
-            e = cc::launch_fill_u32(ctr, (int64_t)(2 * P->splits.size()), 0u, st);
             for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
                 const cc::Split& sp = P->splits[i];
                 cc::StepParamsHost h{};
@@ -330,6 +400,8 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
                 h.col = G->col;
                 h.colour = colour;
                 h.light = G->light;
+                h.light_start = G->light_start;
+                h.n_ranges = G->n_ranges;
                 h.chunks = G->chunks;
                 h.hubs = G->hubs;
                 h.n_light = G->n_light;
@@ -357,6 +429,7 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
                 h.nstride = P->max_stride_N;
                 h.fold = sp.fold_off >= 0 ? (const uint16_t*)(cdev + sp.fold_off) : nullptr;
                 h.split = sp.split_off >= 0 ? (const uint32_t*)(cdev + sp.split_off) : nullptr;
+                h.cols_per_lane = G->cols_per_lane;
                 h.k = P->k;
                 h.s = sp.s;
                 h.a = sp.a;
@@ -366,9 +439,21 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
                 h.Ws = sp.Ws;
                 h.Nw = sp.Nw;
                 h.npairs = sp.npairs;
-                h.counters = ctr + 2 * i;
                 h.n_cu = G->n_cu;
-                e = cc::launch_split(h, st);
+                hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+                if (P->profiling) {
+                    for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+                    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+                }
+                if (e == hipSuccess) e = cc::launch_split(h, st, P->profiling ? ev[1] : nullptr);
+                if (e == hipSuccess && P->profiling) {
+                    e = hipEventRecord(ev[2], st);
+                    auto& pe = P->prof_events[i];
+                    pe.push_back(ev[0]);
+                    pe.push_back(ev[1]);
+                    pe.push_back(ev[2]);
+                    P->prof_launches[i] += 1;
+                }
             }
         }
         if (e == hipSuccess) e = cc::launch_reduce(root_out, n, red, X_dev + b, st);

@@ -60,6 +60,11 @@ struct cc_plan {
     int64_t t3_memory = 0, t3_compute = 0;
     int64_t gather_per_edge = 0, combine_per_vertex = 0;
     int64_t peak_live_cols = 0;
+    // measurement (cc_profile_*): event triples per (colouring, split); opaque hipEvent_t handles
+    bool profiling = false;
+    mutable std::vector<std::vector<void*>> prof_events;  // per split: start, mid, end, start, ...
+    mutable std::vector<int64_t> prof_launches;
+    ~cc_plan();
 };
 
 namespace cc {
@@ -87,10 +92,11 @@ struct StepParamsHost {
     const int64_t* row_ptr;
     const int32_t* col;
     const uint8_t* colour;
-    const int32_t* light;
+    const int32_t* light;        // light rows, heaviest first
+    const int32_t* light_start;  // light range r = light[light_start[r] .. light_start[r+1])
     const ChunkItem* chunks;
     const HubItem* hubs;
-    int64_t n_light, n_chunks, n_hubs;
+    int64_t n_light, n_ranges, n_chunks, n_hubs;
     const double* P;
     const double* A;
     double* O;
@@ -99,7 +105,7 @@ struct StepParamsHost {
     const uint32_t* split;
     int64_t pstride, astride, ostride, nstride;
     int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
-    unsigned* counters;  // two work counters (split kernel, hub finish), zeroed before launch
+    int cols_per_lane;  // 0 = choose from Wp
     int n_cu;
 };
 
@@ -115,7 +121,8 @@ int reduce_blocks_for(int64_t n);
 hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* out, hipStream_t st);
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                            unsigned* flags, hipStream_t st);
-hipError_t launch_split(const StepParamsHost& h, hipStream_t st);
+// mid (optional) is recorded between the gather kernel and the cut-row finish kernel
+hipError_t launch_split(const StepParamsHost& h, hipStream_t st, hipEvent_t mid);
 size_t split_lds_bytes(int Nw, int Wa, int a);
 }  // namespace cc
 
@@ -124,10 +131,12 @@ struct cc_graph {
     const int64_t* row_ptr = nullptr;
     const int32_t* col = nullptr;
     int32_t* light = nullptr;        // device: light rows, heaviest first
+    int32_t* light_start = nullptr;  // device: n_ranges + 1 starts of light ranges
     cc::ChunkItem* chunks = nullptr; // device
     cc::HubItem* hubs = nullptr;     // device
-    int64_t n_light = 0, n_chunks = 0, n_hubs = 0;
+    int64_t n_light = 0, n_ranges = 0, n_chunks = 0, n_hubs = 0;
     int32_t hub_threshold = 0, chunk = 0;
+    int32_t cols_per_lane = 0;
     int device = 0;
     int n_cu = 0;
 };

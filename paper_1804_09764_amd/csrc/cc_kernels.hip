@@ -20,7 +20,8 @@
 // row of at most `hub_threshold` entries is one work item processed by one wavefront; longer rows
 // are cut into chunks of `chunk` entries whose partial neighbour sums go to scratch and are added
 // in chunk order by a second kernel, so every entry has one fixed summation order (no atomics on
-// counts). Work items are handed out through a device counter to persistent workgroups.
+// counts). Light rows are grouped into ranges of about `chunk` entries (at most 64 rows); chunks and
+// ranges are dealt round-robin to persistent wavefronts.
 #include <hip/hip_runtime.h>
 
 #include "cc_internal.h"
@@ -32,9 +33,10 @@ struct StepParams {
     const int32_t* col;
     const uint8_t* colour;
     const int32_t* light;
+    const int32_t* light_start;
     const ChunkItem* chunks;
     const HubItem* hubs;
-    int64_t n_light, n_chunks, n_hubs;
+    int64_t n_light, n_ranges, n_chunks, n_hubs;
     const double* P;
     const double* A;
     double* O;
@@ -45,7 +47,7 @@ struct StepParams {
     int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
     int lds_wave;   // doubles of LDS per wavefront
     int a_off;      // offset of the staged active row inside the wavefront's LDS slice
-    unsigned* counter;
+    int waves_per_block;
 };
 
 __device__ __forceinline__ int lane_id() {
@@ -61,67 +63,121 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// N[0..Nw) += neighbour sums over CSR entries [beg, end) of the passive table (p >= 2)
+// Neighbour sum of one CSR segment into N[0..Nw) (LDS), p >= 2.
+//
+// The segment is read in blocks of 64 entries. The usable neighbours of a block (colour valid and
+// different from col(v)) are sorted by (colour, position) with a lane permutation, then streamed
+// through two register batches of D rows each: the rows of batch b+1 are in flight while batch b
+// is added. Consecutive members of one colour are summed in registers (in member order) and folded
+// into N through the fold map once per colour and block; the fold-map entries of a colour are
+// loaded together with the row of its first member.
+template <int J, int D>
+__device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, int su, int sc, int c0, int cv,
+                                           int lane, double (&X)[D][J], int (&F)[D][J]) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        const int i = b * D + q;
+        if (i < cnt) {
+            const int ui = bcast(su, i);
+            const int ci = bcast(sc, i);
+            const double* row = S.P + (int64_t)ui * S.pstride + c0;
+#pragma unroll
+            for (int t = 0; t < J; ++t) {
+                const int j = c0 + lane + kWave * t;
+                X[q][t] = (j < S.Wp) ? row[lane + kWave * t] : 0.0;
+            }
+            const bool first = (i == 0) || (ci != bcast(sc, i > 0 ? i - 1 : 0));
+            if (first) {
+                const uint16_t* fm = S.fold + ((int64_t)ci * S.k + cv) * S.Wp + c0;
+#pragma unroll
+                for (int t = 0; t < J; ++t) {
+                    const int j = c0 + lane + kWave * t;
+                    F[q][t] = (j < S.Wp) ? (int)fm[lane + kWave * t] : (int)kNoSlot;
+                }
+            }
+        }
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void fold_acc(double* N, const double (&acc)[J], const int (&f)[J]) {
+#pragma unroll
+    for (int t = 0; t < J; ++t)
+        if (f[t] != (int)kNoSlot) N[f[t]] += acc[t];
+}
+
+template <int J, int D>
+__device__ __forceinline__ void consume_batch(int b, int cnt, int sc, int& cur, double* N, double (&acc)[J],
+                                              int (&fcur)[J], const double (&X)[D][J], const int (&F)[D][J]) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        const int i = b * D + q;
+        if (i < cnt) {
+            const int ci = bcast(sc, i);
+            if (ci != cur) {
+                if (cur >= 0) fold_acc<J>(N, acc, fcur);
+                cur = ci;
+#pragma unroll
+                for (int t = 0; t < J; ++t) {
+                    fcur[t] = F[q][t];
+                    acc[t] = X[q][t];
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < J; ++t) acc[t] += X[q][t];
+            }
+        }
+    }
+}
+
 template <int J>
 __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
+    constexpr int D = (J >= 8) ? 2 : 4;  // rows per batch: keeps two batches within the VGPR budget
     const int k = S.k;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int64_t e = e0 + lane;
             const bool valid = e < end;
             const int u = valid ? S.col[e] : 0;
             const int cu = valid ? (int)S.colour[u] : 255;
-            uint64_t rem = __ballot(valid && cu < k && cu != cv);
-            while (rem) {
-                const int first = __ffsll((unsigned long long)rem) - 1;
-                const int c = bcast(cu, first);
-                uint64_t grp = __ballot(cu == c) & rem;
-                rem &= ~grp;
-                double acc[J];
-#pragma unroll
-                for (int t = 0; t < J; ++t) acc[t] = 0.0;
-                while (grp) {
-                    // up to four rows in flight; added in member order
-                    int m[4];
-                    int cnt = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (grp) {
-                            m[q] = __ffsll((unsigned long long)grp) - 1;
-                            grp &= grp - 1;
-                            ++cnt;
-                        } else {
-                            m[q] = m[0];
-                        }
-                    }
-                    double x[4][J];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int uq = bcast(u, m[q]);
-                        const double* row = S.P + (int64_t)uq * S.pstride + c0;
-#pragma unroll
-                        for (int t = 0; t < J; ++t) {
-                            const int j = c0 + lane + kWave * t;
-                            x[q][t] = (q < cnt && j < S.Wp) ? row[lane + kWave * t] : 0.0;
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (q < cnt) {
-#pragma unroll
-                            for (int t = 0; t < J; ++t) acc[t] += x[q][t];
-                        }
-                }
-                const uint16_t* fm = S.fold + ((int64_t)c * k + cv) * S.Wp;
-#pragma unroll
-                for (int t = 0; t < J; ++t) {
-                    const int j = c0 + lane + kWave * t;
-                    if (j < S.Wp) {
-                        const uint16_t idx = fm[j];
-                        if (idx != kNoSlot) N[idx] += acc[t];
-                    }
-                }
+            const bool use = valid && cu < k && cu != cv;
+            const uint64_t used = __ballot(use);
+            const int cnt = __popcll((unsigned long long)used);
+            if (cnt == 0) continue;
+            // position of this lane in (colour, lane) order; unused lanes go after the used ones
+            int rank = use ? 0 : cnt + __popcll((unsigned long long)(~used & below));
+            for (int c = 0; c < k; ++c) {
+                const uint64_t bc = __ballot(use && cu == c);
+                if (use && cu > c) rank += __popcll((unsigned long long)bc);
+                if (use && cu == c) rank += __popcll((unsigned long long)(bc & below));
             }
+            const int su = __builtin_amdgcn_ds_permute(rank << 2, u);
+            const int sc = __builtin_amdgcn_ds_permute(rank << 2, cu);
+            double acc[J];
+            int fcur[J];
+            double XA[D][J], XB[D][J];
+            int FA[D][J], FB[D][J];
+#pragma unroll
+            for (int t = 0; t < J; ++t) {
+                acc[t] = 0.0;
+                fcur[t] = (int)kNoSlot;
+            }
+#pragma unroll
+            for (int q = 0; q < D; ++q)
+#pragma unroll
+                for (int t = 0; t < J; ++t) FA[q][t] = FB[q][t] = (int)kNoSlot;
+            int cur = -1;
+            const int nb = (cnt + D - 1) / D;
+            load_batch<J, D>(S, 0, cnt, su, sc, c0, cv, lane, XA, FA);
+            for (int b = 0; b < nb; b += 2) {
+                if (b + 1 < nb) load_batch<J, D>(S, b + 1, cnt, su, sc, c0, cv, lane, XB, FB);
+                consume_batch<J, D>(b, cnt, sc, cur, N, acc, fcur, XA, FA);
+                if (b + 1 >= nb) break;
+                if (b + 2 < nb) load_batch<J, D>(S, b + 2, cnt, su, sc, c0, cv, lane, XA, FA);
+                consume_batch<J, D>(b + 1, cnt, sc, cur, N, acc, fcur, XB, FB);
+            }
+            fold_acc<J>(N, acc, fcur);
         }
     }
 }
@@ -184,6 +240,29 @@ __device__ void combine_store(const StepParams& S, int v, double* N, double* Ash
     }
 }
 
+// one light row: neighbour sum into LDS, then combine and store
+template <int J>
+__device__ __forceinline__ void light_row(const StepParams& S, int v, double* N, double* Ash, int lane) {
+    const int64_t beg = S.row_ptr[v];
+    const int64_t end = S.row_ptr[v + 1];
+    // a vertex without a valid colour (>= k) roots no colourful embedding
+    const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
+    if (beg == end || cv >= S.k) {
+        double* orow = S.O + (int64_t)v * S.ostride;
+        for (int r = lane; r < S.Ws; r += kWave) orow[r] = 0.0;
+        return;
+    }
+    for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
+    wave_sync_lds();
+    if (S.p == 1) count_colours(S, beg, end, cv, N, lane);
+    else gather_fold<J>(S, beg, end, cv, N, lane);
+    wave_sync_lds();
+    combine_store(S, v, N, Ash, lane);
+    wave_sync_lds();
+}
+
+// Tasks (chunks of cut rows first, then ranges of light rows, all of about `chunk` entries) are
+// dealt to the persistent wavefronts round-robin: no shared counter, one fixed owner per task.
 template <int J>
 __global__ __launch_bounds__(256) void k_split(StepParams S) {
     extern __shared__ double lds[];
@@ -191,47 +270,28 @@ __global__ __launch_bounds__(256) void k_split(StepParams S) {
     const int wib = threadIdx.x / kWave;
     double* N = lds + (int64_t)wib * S.lds_wave;
     double* Ash = N + S.a_off;
-    const int64_t total = S.n_chunks + S.n_light;
-    for (;;) {
-        unsigned it = 0;
-        if (lane == 0) it = atomicAdd(S.counter, 1u);
-        const int64_t item = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)it);
-        if (item >= total) break;
-        int v;
-        int64_t beg, end;
-        const bool is_chunk = item < S.n_chunks;
-        if (is_chunk) {
-            const ChunkItem ch = S.chunks[item];
-            v = ch.v;
-            beg = ch.beg;
-            end = ch.beg + ch.len;
-        } else {
-            v = S.light[item - S.n_chunks];
-            beg = S.row_ptr[v];
-            end = S.row_ptr[v + 1];
-        }
-        v = __builtin_amdgcn_readfirstlane(v);
-        // a vertex without a valid colour (>= k) roots no colourful embedding
-        const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
-        if (!is_chunk && (beg == end || cv >= S.k)) {
-            double* orow = S.O + (int64_t)v * S.ostride;
-            for (int r = lane; r < S.Ws; r += kWave) orow[r] = 0.0;
-            continue;
-        }
-        for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
-        wave_sync_lds();
-        if (cv < S.k) {
-            if (S.p == 1) count_colours(S, beg, end, cv, N, lane);
-            else gather_fold<J>(S, beg, end, cv, N, lane);
-        }
-        wave_sync_lds();
-        if (is_chunk) {
-            double* prow = S.partial + item * S.nstride;
+    const int64_t n_tasks = S.n_chunks + S.n_ranges;
+    const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
+    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves) {
+        if (t < S.n_chunks) {
+            const ChunkItem ch = S.chunks[t];
+            const int v = __builtin_amdgcn_readfirstlane(ch.v);
+            const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
+            for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
+            wave_sync_lds();
+            if (cv < S.k) {
+                if (S.p == 1) count_colours(S, ch.beg, ch.beg + ch.len, cv, N, lane);
+                else gather_fold<J>(S, ch.beg, ch.beg + ch.len, cv, N, lane);
+            }
+            wave_sync_lds();
+            double* prow = S.partial + t * S.nstride;
             for (int r = lane; r < S.Nw; r += kWave) prow[r] = N[r];
+            wave_sync_lds();
         } else {
-            combine_store(S, v, N, Ash, lane);
+            const int64_t r = t - S.n_chunks;
+            const int i0 = S.light_start[r], i1 = S.light_start[r + 1];
+            for (int i = i0; i < i1; ++i) light_row<J>(S, S.light[i], N, Ash, lane);
         }
-        wave_sync_lds();
     }
 }
 
@@ -242,12 +302,9 @@ __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
     const int wib = threadIdx.x / kWave;
     double* N = lds + (int64_t)wib * S.lds_wave;
     double* Ash = N + S.a_off;
-    for (;;) {
-        unsigned it = 0;
-        if (lane == 0) it = atomicAdd(S.counter, 1u);
-        const int64_t item = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)it);
-        if (item >= S.n_hubs) break;
-        const HubItem h = S.hubs[item];
+    const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
+    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves) {
+        const HubItem h = S.hubs[t];
         for (int r = lane; r < S.Nw; r += kWave) {
             double sum = 0.0;
             const double* pp = S.partial + h.first_chunk * S.nstride + r;
@@ -407,19 +464,19 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n
     return hipGetLastError();
 }
 
-// columns per lane per pass of the passive row
-static int pick_J(int Wp) {
+// passive-row doubles per lane per pass
+static int pick_J(int Wp, int want) {
+    if (want == 1 || want == 2 || want == 4 || want == 8) return want;
     if (Wp <= 64) return 1;
     if (Wp <= 128) return 2;
-    if (Wp <= 256) return 4;
-    return 8;
+    return 4;
 }
 
-hipError_t launch_split(const StepParamsHost& h, hipStream_t st) {
+hipError_t launch_split(const StepParamsHost& h, hipStream_t st, hipEvent_t mid) {
     StepParams S;
     S.row_ptr = h.row_ptr; S.col = h.col; S.colour = h.colour;
-    S.light = h.light; S.chunks = h.chunks; S.hubs = h.hubs;
-    S.n_light = h.n_light; S.n_chunks = h.n_chunks; S.n_hubs = h.n_hubs;
+    S.light = h.light; S.light_start = h.light_start; S.chunks = h.chunks; S.hubs = h.hubs;
+    S.n_light = h.n_light; S.n_ranges = h.n_ranges; S.n_chunks = h.n_chunks; S.n_hubs = h.n_hubs;
     S.P = h.P; S.A = h.A; S.O = h.O; S.partial = h.partial;
     S.fold = h.fold; S.split = h.split;
     S.pstride = h.pstride; S.astride = h.astride; S.ostride = h.ostride; S.nstride = h.nstride;
@@ -435,8 +492,9 @@ hipError_t launch_split(const StepParamsHost& h, hipStream_t st) {
         waves_per_block >>= 1;
     if ((size_t)S.lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
     const int threads = waves_per_block * kWave;
+    S.waves_per_block = waves_per_block;
     const size_t lds = (size_t)S.lds_wave * waves_per_block * sizeof(double);
-    int J = (h.p >= 2) ? pick_J(h.Wp) : 1;
+    int J = (h.p >= 2) ? pick_J(h.Wp, h.cols_per_lane) : 1;
     const void* fn = nullptr;
     switch (J) {
         case 1: fn = (const void*)k_split<1>; break;
@@ -448,12 +506,11 @@ hipError_t launch_split(const StepParamsHost& h, hipStream_t st) {
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
     if (err != hipSuccess) return err;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const int64_t total = h.n_chunks + h.n_light;
+    const int64_t total = h.n_chunks + h.n_ranges;
     int64_t blocks = (int64_t)per_cu * h.n_cu;
     const int64_t need = (total + waves_per_block - 1) / waves_per_block;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
-    S.counter = h.counters;
     if (total > 0) {
         switch (J) {
             case 1: hipLaunchKernelGGL(k_split<1>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
@@ -464,8 +521,11 @@ hipError_t launch_split(const StepParamsHost& h, hipStream_t st) {
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
+    if (mid) {
+        err = hipEventRecord(mid, st);
+        if (err != hipSuccess) return err;
+    }
     if (h.n_hubs > 0) {
-        S.counter = h.counters + 1;
         int per_cu2 = 0;
         err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_hub_finish, threads, lds);
         if (err != hipSuccess) return err;

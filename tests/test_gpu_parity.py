@@ -32,10 +32,10 @@ def assert_parity(gpu, ref):
         assert rel.max() <= 1e-12, rel.max()
 
 
-def gpu_count(rp, cl, col, T, root=-1, hub_threshold=0, chunk=0, flags=0):
+def gpu_count(rp, cl, col, T, root=-1, hub_threshold=0, chunk=0, flags=0, cols_per_lane=0):
     import torch
     cc = _cc()
-    G = cc.Graph.from_numpy(rp, cl, hub_threshold=hub_threshold, chunk=chunk)
+    G = cc.Graph.from_numpy(rp, cl, hub_threshold=hub_threshold, chunk=chunk, cols_per_lane=cols_per_lane)
     P = cc.Plan(T, root=root, flags=flags)
     colours = torch.from_numpy(np.ascontiguousarray(col, dtype=np.uint8)).cuda().view(1, -1)
     X, V = cc.count(P, G, colours, per_vertex=True)
@@ -121,8 +121,9 @@ def test_wide_tables(dev, k):
     col = inputs.colours(len(rp) - 1, k, 1)
     for seed in (12, 13):
         T = inputs.pruefer_tree(k, seed)
-        print(f"case: rmat8 wide k={k} seed={seed}", flush=True)
-        check_case(rp, cl, col, T, hub_threshold=128, chunk=64)
+        for cols in (0, 1, 2, 8):
+            print(f"case: rmat8 wide k={k} seed={seed} cols_per_lane={cols}", flush=True)
+            check_case(rp, cl, col, T, hub_threshold=128, chunk=64, cols_per_lane=cols)
     check_case(rp, cl, col, inputs.path_tree(k))
 
 
