@@ -186,6 +186,52 @@ cc_status cc_count(const cc_plan* plan, const cc_graph* g, const uint8_t* colour
                    void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Batched count: many colourings and templates, on one or more graphs, in one launch          */
+/* (the independent outer iterations of Algorithm 1 run together)                              */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct {
+    const cc_plan* plan;         /* bound to device memory (cc_plan_bind_device) */
+    const cc_graph* graph;
+    const uint8_t* colours_dev;  /* n bytes: one colouring of the graph, values in [0, plan k) */
+    double* X_dev;               /* 1 double: receives X for this colouring */
+    double* vertex_dev;          /* optional n doubles of per-vertex counts (NULL = not kept) */
+} cc_instance;
+
+typedef struct cc_batch cc_batch;
+
+#define CC_BATCH_LEVELS 1u  /* one launch per dependency level instead of one persistent launch */
+/* The persistent launch sizes its grid to the device's resident capacity; a batch that may run
+ * concurrently with d-1 other persistent batches must take at most 1/d of it, set as
+ * CC_BATCH_SHARE(d) (1 <= d <= 255), so that all their workgroups can be resident together. */
+#define CC_BATCH_SHARE(d) (((uint32_t)(d) & 0xFFu) << 8)
+
+/*
+ * Prepare a batch of n_inst instances (host only; the instance array is copied). Every instance
+ * computes exactly what cc_count computes for its plan, graph and colouring, bit for bit: the
+ * kernels and the per-entry summation order are the same. By default all splits of all instances
+ * run in one persistent launch in which work items wait on per-(instance, split) completion
+ * counters; CC_BATCH_LEVELS runs one launch per dependency level instead.
+ */
+cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flags, cc_batch** out);
+
+/* Device workspace needed by cc_batch_run (tables of every instance are resident together). */
+cc_status cc_batch_workspace_bytes(const cc_batch* batch, size_t* bytes);
+
+/*
+ * Queue the batch on `stream`. The batch object, its plans and graphs and all buffers must stay
+ * alive until the work has finished; a batch may be run again only after its previous run has
+ * finished.
+ */
+cc_status cc_batch_run(cc_batch* batch, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Synchronise `stream` and report whether the last run completed (CC_EINTERNAL if a dependency
+ * wait inside the persistent launch gave up). */
+cc_status cc_batch_check(cc_batch* batch, void* stream);
+
+void cc_batch_destroy(cc_batch* batch);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Measurement                                                                                  */
 /* ------------------------------------------------------------------------------------------ */
 

@@ -51,7 +51,7 @@ def _lib():
                                    ctypes.c_double, ctypes.c_uint64, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.gen_rmat_fill.restype = ctypes.c_int
-    lib.gen_rmat_fill.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.gen_rmat_fill.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     lib.gen_free.restype = None
     lib.gen_free.argtypes = [ctypes.c_void_p]
     lib.gen_rmat_params.restype = None
@@ -196,7 +196,7 @@ def rmat_graph(scale: int, edge_factor: int, seed: int, abc=RMAT_ABC, threads: i
     try:
         row_ptr = np.empty(n.value + 1, dtype=np.int64)
         col = np.empty(max(nnz.value, 1), dtype=np.int32)[: nnz.value]
-        lib.gen_rmat_fill(h, row_ptr.ctypes.data, col.ctypes.data)
+        lib.gen_rmat_fill(h, row_ptr.ctypes.data, col.ctypes.data, threads)
     finally:
         lib.gen_free(h)
     return row_ptr, col

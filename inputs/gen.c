@@ -99,12 +99,12 @@ void gen_rmat_params(int scale, double a, double b, double c, uint64_t seed, uin
 void* gen_rmat_build(int scale, int64_t edge_factor, double a, double b, double c, uint64_t seed,
                      int threads, int64_t* n_out, int64_t* nnz_out) {
     if (scale < 1 || scale > 30 || edge_factor < 1) return NULL;
-    if (threads > 0) omp_set_num_threads(threads);
+    if (threads <= 0) threads = omp_get_max_threads();
     rmat_params P;
     uint64_t k8[8];
     gen_rmat_params(scale, a, b, c, seed, k8);
     P.scale = scale;
-    P.mask = (scale == 64) ? ~0ULL : ((1ULL << scale) - 1);
+    P.mask = (1ULL << scale) - 1;
     P.ta = (uint32_t)k8[0]; P.tb = (uint32_t)k8[1]; P.tc = (uint32_t)k8[2];
     P.p1 = k8[3]; P.q1 = k8[4]; P.p2 = k8[5]; P.q2 = k8[6];
     P.shift = (int)k8[7];
@@ -112,46 +112,59 @@ void* gen_rmat_build(int scale, int64_t edge_factor, double a, double b, double 
 
     const int64_t n = (int64_t)1 << scale;
     const uint64_t E = (uint64_t)edge_factor << scale;
+    const int T = threads;
 
     gen_handle* h = (gen_handle*)calloc(1, sizeof(gen_handle));
-    if (!h) return NULL;
+    int64_t* cnt = (int64_t*)calloc((size_t)T * (size_t)n, sizeof(int64_t));  /* per-thread degrees */
+    int64_t* off = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!h || !cnt || !off) { free(h); free(cnt); free(off); return NULL; }
     h->n = n;
-    int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
-    if (!deg) { free(h); return NULL; }
 
-    /* pass 1: degree of every endpoint (both directions) */
-#pragma omp parallel for schedule(static)
-    for (uint64_t e = 0; e < E; ++e) {
-        uint32_t s, d;
-        if (draw(&P, e, &s, &d)) {
-            __atomic_fetch_add(&deg[s], 1, __ATOMIC_RELAXED);
-            __atomic_fetch_add(&deg[d], 1, __ATOMIC_RELAXED);
+    /* pass 1: each thread counts the endpoints of its own contiguous range of edge draws */
+#pragma omp parallel num_threads(T)
+    {
+        const int t = omp_get_thread_num();
+        const uint64_t lo = E * (uint64_t)t / (uint64_t)T, hi = E * (uint64_t)(t + 1) / (uint64_t)T;
+        int64_t* my = cnt + (size_t)t * (size_t)n;
+        for (uint64_t e = lo; e < hi; ++e) {
+            uint32_t s, d;
+            if (draw(&P, e, &s, &d)) { my[s]++; my[d]++; }
         }
     }
-    int64_t* off = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
-    if (!off) { free(deg); free(h); return NULL; }
+    /* row offsets, and per-thread write cursors (thread t writes after threads < t) */
     off[0] = 0;
-    for (int64_t v = 0; v < n; ++v) off[v + 1] = off[v] + deg[v];
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t acc = off[v];
+        for (int t = 0; t < T; ++t) {
+            int64_t x = cnt[(size_t)t * (size_t)n + (size_t)v];
+            cnt[(size_t)t * (size_t)n + (size_t)v] = acc;
+            acc += x;
+        }
+        off[v + 1] = acc;
+    }
     const int64_t raw_n = off[n];
     int32_t* raw = (int32_t*)malloc((size_t)(raw_n > 0 ? raw_n : 1) * sizeof(int32_t));
-    if (!raw) { free(off); free(deg); free(h); return NULL; }
-    /* cursors */
-    memcpy(deg, off, (size_t)n * sizeof(int64_t));
+    if (!raw) { free(off); free(cnt); free(h); return NULL; }
 
-    /* pass 2: scatter both directions */
-#pragma omp parallel for schedule(static)
-    for (uint64_t e = 0; e < E; ++e) {
-        uint32_t s, d;
-        if (draw(&P, e, &s, &d)) {
-            int64_t ps = __atomic_fetch_add(&deg[s], 1, __ATOMIC_RELAXED);
-            int64_t pd = __atomic_fetch_add(&deg[d], 1, __ATOMIC_RELAXED);
-            raw[ps] = (int32_t)d;
-            raw[pd] = (int32_t)s;
+    /* pass 2: the same draws, scattered through the thread's own cursors (no atomics) */
+#pragma omp parallel num_threads(T)
+    {
+        const int t = omp_get_thread_num();
+        const uint64_t lo = E * (uint64_t)t / (uint64_t)T, hi = E * (uint64_t)(t + 1) / (uint64_t)T;
+        int64_t* cur = cnt + (size_t)t * (size_t)n;
+        for (uint64_t e = lo; e < hi; ++e) {
+            uint32_t s, d;
+            if (draw(&P, e, &s, &d)) {
+                raw[cur[s]++] = (int32_t)d;
+                raw[cur[d]++] = (int32_t)s;
+            }
         }
     }
+    free(cnt);
+    int64_t* uniq = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!uniq) { free(raw); free(off); free(h); return NULL; }
     /* sort + unique per row */
-    int64_t* uniq = deg; /* reuse */
-#pragma omp parallel for schedule(dynamic, 256)
+#pragma omp parallel for schedule(dynamic, 256) num_threads(T)
     for (int64_t v = 0; v < n; ++v) {
         int32_t* r = raw + off[v];
         int64_t len = off[v + 1] - off[v];
@@ -172,13 +185,14 @@ void* gen_rmat_build(int scale, int64_t edge_factor, double a, double b, double 
     return h;
 }
 
-int gen_rmat_fill(void* hv, int64_t* row_ptr, int32_t* col) {
+int gen_rmat_fill(void* hv, int64_t* row_ptr, int32_t* col, int threads) {
     gen_handle* h = (gen_handle*)hv;
     if (!h) return -1;
+    if (threads <= 0) threads = omp_get_max_threads();
     const int64_t n = h->n;
     row_ptr[0] = 0;
     for (int64_t v = 0; v < n; ++v) row_ptr[v + 1] = row_ptr[v] + h->uniq[v];
-#pragma omp parallel for schedule(dynamic, 1024)
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(threads)
     for (int64_t v = 0; v < n; ++v)
         memcpy(col + row_ptr[v], h->raw + h->raw_off[v], (size_t)h->uniq[v] * sizeof(int32_t));
     return 0;

@@ -52,6 +52,18 @@ class _GraphInfo(ctypes.Structure):
                 ("cols_per_lane", ctypes.c_int32)]
 
 
+class _Instance(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("graph", ctypes.c_void_p), ("colours_dev", ctypes.c_void_p),
+                ("X_dev", ctypes.c_void_p), ("vertex_dev", ctypes.c_void_p)]
+
+
+CC_BATCH_LEVELS = 1
+
+
+def CC_BATCH_SHARE(d: int) -> int:
+    return (d & 0xFF) << 8
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("cols_per_lane", ctypes.c_int32)]
@@ -60,7 +72,8 @@ class _Tuning(ctypes.Structure):
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
            "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
-           "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read"]
+           "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read",
+           "cc_batch_create", "cc_batch_workspace_bytes", "cc_batch_run", "cc_batch_check", "cc_batch_destroy"]
 
 
 @lru_cache(maxsize=1)
@@ -91,6 +104,11 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_double)]),
         "cc_estimate_median_of_means": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ctypes.c_double)]),
         "cc_profile_enable": (ctypes.c_int, [P, I32]),
+        "cc_batch_create": (ctypes.c_int, [I32, P, U32, ctypes.POINTER(P)]),
+        "cc_batch_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "cc_batch_run": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
+        "cc_batch_check": (ctypes.c_int, [P, P]),
+        "cc_batch_destroy": (None, [P]),
         "cc_profile_read": (ctypes.c_int, [P, I32, P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -308,3 +326,65 @@ def estimate_median_of_means(plan: Plan, X, groups: int) -> float:
     est = ctypes.c_double()
     _check(lib().cc_estimate_median_of_means(plan.handle, x.ctypes.data, len(x), groups, ctypes.byref(est)))
     return est.value
+
+
+class Batch:
+    """Many (plan, graph, colouring) instances counted in one persistent launch (cc_batch_*).
+
+    `instances` is a list of (plan, graph, colours, X_out, vertex_out) with colours a uint8 GPU
+    tensor of n entries, X_out a float64 GPU tensor view of one element and vertex_out either
+    None or a float64 GPU tensor of n entries. Every instance gets exactly the result that
+    count() would give it alone.
+    """
+
+    def __init__(self, instances, levels: bool = False, share: int = 1):
+        import torch
+        self._keep = list(instances)
+        arr = (_Instance * max(len(instances), 1))()
+        for i, (plan, graph, col, X, V) in enumerate(instances):
+            if col.numel() != graph.n:
+                raise ValueError("colours must have n entries")
+            arr[i].plan = plan.handle.value
+            arr[i].graph = graph.handle.value
+            arr[i].colours_dev = _dev_ptr(col, torch.uint8, "colours").value if graph.n else None
+            arr[i].X_dev = _dev_ptr(X, torch.float64, "X").value
+            arr[i].vertex_dev = _dev_ptr(V, torch.float64, "vertex_out").value if V is not None else None
+        flags = (CC_BATCH_LEVELS if levels else 0) | CC_BATCH_SHARE(share)
+        h = ctypes.c_void_p()
+        _check(lib().cc_batch_create(len(instances), arr, flags, ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(lib().cc_batch_workspace_bytes(self._h, ctypes.byref(nb)))
+        self.workspace_bytes = nb.value
+        self._dev = instances[0][1].row_ptr.device if instances else None
+
+    def run(self, workspace: Workspace | None = None, stream=None):
+        ws = (workspace or Workspace()).get(self.workspace_bytes, self._dev)
+        self._ws = ws
+        _check(lib().cc_batch_run(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+
+    def check(self, stream=None):
+        _check(lib().cc_batch_check(self._h, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().cc_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def count_batched(plans, graph: Graph, colours, levels: bool = False, workspace: Workspace | None = None,
+                  stream=None):
+    """X[t, b] for every plan t and colouring row b of `colours` ([B, n] uint8) in one batch."""
+    import torch
+    if colours.dim() == 1:
+        colours = colours.view(1, -1)
+    B = colours.shape[0]
+    X = torch.empty((len(plans), B), dtype=torch.float64, device=graph.row_ptr.device)
+    inst = [(p, graph, colours[b], X[t, b:b + 1], None) for t, p in enumerate(plans) for b in range(B)]
+    batch = Batch(inst, levels=levels)
+    batch.run(workspace, stream)
+    return X, batch

@@ -75,6 +75,59 @@ CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
     return L;
 }
 
+// arguments of split `sp` of plan P on graph G for one colouring; tables live in `arena`
+cc::StepParams step_params(const cc_plan* P, const cc_graph* G, const cc::Split& sp, const uint8_t* colour,
+                           double* arena, int64_t n_pad, double* partial, double* root_out) {
+    cc::StepParams h{};
+    h.row_ptr = G->row_ptr;
+    h.col = G->col;
+    h.colour = colour;
+    h.light = G->light;
+    h.light_start = G->light_start;
+    h.chunks = G->chunks;
+    h.hubs = G->hubs;
+    h.n_light = G->n_light;
+    h.n_ranges = G->n_ranges;
+    h.n_chunks = G->n_chunks;
+    h.n_hubs = G->n_hubs;
+    if (sp.pas >= 0) {
+        const cc::Table& t = P->tables[sp.pas];
+        h.P = arena + t.col_off * n_pad;
+        h.pstride = t.stride;
+    }
+    if (sp.act >= 0) {
+        const cc::Table& t = P->tables[sp.act];
+        h.A = arena + t.col_off * n_pad;
+        h.astride = t.stride;
+    }
+    if (sp.out >= 0) {
+        const cc::Table& t = P->tables[sp.out];
+        h.O = arena + t.col_off * n_pad;
+        h.ostride = t.stride;
+    } else {
+        h.O = root_out;
+        h.ostride = 1;
+    }
+    const uint8_t* cdev = (const uint8_t*)P->dev;
+    h.partial = partial;
+    h.nstride = P->max_stride_N;
+    h.fold = sp.fold_off >= 0 ? (const uint16_t*)(cdev + sp.fold_off) : nullptr;
+    h.split = sp.split_off >= 0 ? (const uint32_t*)(cdev + sp.split_off) : nullptr;
+    h.cols_per_lane = G->cols_per_lane;
+    h.k = P->k;
+    h.s = sp.s;
+    h.a = sp.a;
+    h.p = sp.p;
+    h.Wa = sp.Wa;
+    h.Wp = sp.Wp;
+    h.Ws = sp.Ws;
+    h.Nw = sp.Nw;
+    h.npairs = sp.npairs;
+    h.a_off = cc::split_a_off(sp.Nw);
+    h.lds_wave = cc::split_lds_wave(sp.Nw, sp.Wa, sp.a);
+    return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -379,7 +432,6 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
     double* partial = (double*)(ws + L.partial_off);
     double* red = (double*)(ws + L.red_off);
     const int64_t n = G->n;
-    const uint8_t* cdev = (const uint8_t*)P->dev;
     hipError_t e = hipSuccess;
     for (int32_t b = 0; b < B; ++b) {
         double* root_out = vertex_dev ? vertex_dev + (int64_t)b * n : (double*)(ws + L.root_off);
@@ -395,57 +447,13 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
         } else {
             for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
                 const cc::Split& sp = P->splits[i];
-                cc::StepParamsHost h{};
-                h.row_ptr = G->row_ptr;
-                h.col = G->col;
-                h.colour = colour;
-                h.light = G->light;
-                h.light_start = G->light_start;
-                h.n_ranges = G->n_ranges;
-                h.chunks = G->chunks;
-                h.hubs = G->hubs;
-                h.n_light = G->n_light;
-                h.n_chunks = G->n_chunks;
-                h.n_hubs = G->n_hubs;
-                if (sp.pas >= 0) {
-                    const cc::Table& t = P->tables[sp.pas];
-                    h.P = arena + t.col_off * L.n_pad;
-                    h.pstride = t.stride;
-                }
-                if (sp.act >= 0) {
-                    const cc::Table& t = P->tables[sp.act];
-                    h.A = arena + t.col_off * L.n_pad;
-                    h.astride = t.stride;
-                }
-                if (sp.out >= 0) {
-                    const cc::Table& t = P->tables[sp.out];
-                    h.O = arena + t.col_off * L.n_pad;
-                    h.ostride = t.stride;
-                } else {
-                    h.O = root_out;
-                    h.ostride = 1;
-                }
-                h.partial = partial;
-                h.nstride = P->max_stride_N;
-                h.fold = sp.fold_off >= 0 ? (const uint16_t*)(cdev + sp.fold_off) : nullptr;
-                h.split = sp.split_off >= 0 ? (const uint32_t*)(cdev + sp.split_off) : nullptr;
-                h.cols_per_lane = G->cols_per_lane;
-                h.k = P->k;
-                h.s = sp.s;
-                h.a = sp.a;
-                h.p = sp.p;
-                h.Wa = sp.Wa;
-                h.Wp = sp.Wp;
-                h.Ws = sp.Ws;
-                h.Nw = sp.Nw;
-                h.npairs = sp.npairs;
-                h.n_cu = G->n_cu;
+                cc::StepParams h = step_params(P, G, sp, colour, arena, L.n_pad, partial, root_out);
                 hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
                 if (P->profiling) {
                     for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
                     if (e == hipSuccess) e = hipEventRecord(ev[0], st);
                 }
-                if (e == hipSuccess) e = cc::launch_split(h, st, P->profiling ? ev[1] : nullptr);
+                if (e == hipSuccess) e = cc::launch_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
                 if (e == hipSuccess && P->profiling) {
                     e = hipEventRecord(ev[2], st);
                     auto& pe = P->prof_events[i];
@@ -461,6 +469,210 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
     }
     return CC_OK;
 }
+
+cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flags, cc_batch** out) {
+    if (!out) return fail(CC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(CC_EINVAL, "bad instance array");
+    cc_batch* B = new (std::nothrow) cc_batch();
+    if (!B) return fail(CC_ENOMEM, "batch allocation failed");
+    B->flags = flags;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    try {
+        B->inst.resize((size_t)n_inst);
+        std::vector<std::vector<int>> seg_of;  // per instance: final segment of each split
+        std::vector<cc_batch::Seg> segs;
+        for (int32_t i = 0; i < n_inst; ++i) {
+            const cc_instance& in = inst[i];
+            if (!in.plan || !in.graph || !in.X_dev || (in.graph->n > 0 && !in.colours_dev)) {
+                delete B;
+                return fail(CC_EINVAL, "instance " + std::to_string(i) + ": NULL plan, graph or buffer");
+            }
+            if (!in.plan->splits.empty() && !in.plan->dev) {
+                delete B;
+                return fail(CC_EINVAL, "instance " + std::to_string(i) + ": plan not bound to device memory");
+            }
+            const cc_plan* P = in.plan;
+            const cc_graph* G = in.graph;
+            if (B->n_cu == 0) B->n_cu = G->n_cu;
+            cc_batch::Inst& I = B->inst[(size_t)i];
+            I.in = in;
+            const int64_t n_pad = pad32(G->n);
+            I.arena_off = take((size_t)P->arena_cols * (size_t)n_pad * sizeof(double));
+            I.partial_off = take((size_t)G->n_chunks * (size_t)P->max_stride_N * sizeof(double));
+            I.root_off = in.vertex_dev ? 0 : take((size_t)std::max<int64_t>(G->n, 1) * sizeof(double));
+            I.red_off = take(1024 * sizeof(double));
+            B->max_red_blocks = std::max(B->max_red_blocks, cc::reduce_blocks_for(G->n));
+            if (G->n == 0) continue;
+            // segments of this instance in plan order, each waiting for the previous one: the
+            // instance's splits share its table arena (first-fit reuse) and its chunk-partial
+            // scratch, so a split may overwrite what an earlier split reads; running them in plan
+            // order, as a plain count does, removes every such hazard. Instances run side by side.
+            std::vector<int> last(P->splits.size(), -1);
+            for (size_t j = 0; j < P->splits.size(); ++j) {
+                const cc::Split& sp = P->splits[j];
+                cc_batch::Seg a{};
+                a.inst = i;
+                a.split = (int)j;
+                a.phase = 0;
+                a.n_items = G->n_chunks + G->n_ranges;
+                a.ndep = 0;
+                a.level = 0;
+                if (j > 0) {
+                    const int d = last[j - 1];
+                    a.dep[a.ndep++] = d;
+                    a.level = segs[(size_t)d].level + 1;
+                }
+                segs.push_back(a);
+                last[j] = (int)segs.size() - 1;
+                if (G->n_hubs > 0) {
+                    cc_batch::Seg h{};
+                    h.inst = i;
+                    h.split = (int)j;
+                    h.phase = 1;
+                    h.n_items = G->n_hubs;
+                    h.ndep = 1;
+                    h.dep[0] = last[j];
+                    h.level = a.level + 1;
+                    segs.push_back(h);
+                    last[j] = (int)segs.size() - 1;
+                }
+                if (sp.p >= 2)
+                    B->J = std::max(B->J, cc::pick_J(sp.Wp, G->cols_per_lane));
+                B->lds_wave = std::max(B->lds_wave, cc::split_lds_wave(sp.Nw, sp.Wa, sp.a));
+            }
+        }
+        // launch order: by level, then instance, split, phase; dependencies renumbered
+        std::vector<int> order(segs.size());
+        for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return segs[(size_t)x].level < segs[(size_t)y].level; });
+        std::vector<int> pos(segs.size());
+        for (size_t q = 0; q < order.size(); ++q) pos[(size_t)order[q]] = (int)q;
+        B->segs.resize(segs.size());
+        int max_level = -1;
+        for (size_t q = 0; q < order.size(); ++q) {
+            cc_batch::Seg sg = segs[(size_t)order[q]];
+            for (int d = 0; d < sg.ndep; ++d) sg.dep[d] = pos[(size_t)sg.dep[d]];
+            B->segs[q] = sg;
+            max_level = std::max(max_level, sg.level);
+        }
+        int64_t item = 0;
+        B->level_start.assign((size_t)(max_level + 2), 0);
+        int lvl = 0;
+        for (size_t q = 0; q < B->segs.size(); ++q) {
+            while (lvl <= B->segs[q].level) B->level_start[(size_t)lvl++] = item;
+            item += B->segs[q].n_items;
+        }
+        while (lvl <= max_level + 1) B->level_start[(size_t)lvl++] = item;
+        if (B->lds_wave == 0) B->lds_wave = 16;
+        B->done_off = take(std::max<size_t>(B->segs.size(), 1) * sizeof(unsigned));
+        B->err_off = take(sizeof(unsigned));
+        B->seg_off = take(std::max<size_t>(B->segs.size(), 1) * sizeof(cc::SegDesc));
+        B->rd_off = take(std::max<size_t>((size_t)n_inst, 1) * sizeof(cc::ReduceDesc));
+        B->total = off;
+        B->seg_host.resize(B->segs.size());
+        B->rd_host.resize((size_t)n_inst);
+    } catch (const std::bad_alloc&) {
+        delete B;
+        return fail(CC_ENOMEM, "host allocation failed while preparing the batch");
+    }
+    *out = B;
+    return CC_OK;
+}
+
+cc_status cc_batch_workspace_bytes(const cc_batch* B, size_t* bytes) {
+    if (!B || !bytes) return fail(CC_EINVAL, "NULL argument");
+    *bytes = B->total;
+    return CC_OK;
+}
+
+cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (!B || (!ws_dev && B->total > 0)) return fail(CC_EINVAL, "NULL argument");
+    if (ws_bytes < B->total) return fail(CC_ENOSPC, "batch workspace too small");
+    if (B->inst.empty()) return CC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)ws_dev;
+    unsigned* done = (unsigned*)(ws + B->done_off);
+    B->err_dev = (unsigned*)(ws + B->err_off);
+    cc::SegDesc* seg_dev = (cc::SegDesc*)(ws + B->seg_off);
+    cc::ReduceDesc* rd_dev = (cc::ReduceDesc*)(ws + B->rd_off);
+    int64_t item = 0;
+    for (size_t q = 0; q < B->segs.size(); ++q) {
+        const cc_batch::Seg& sg = B->segs[q];
+        const cc_batch::Inst& I = B->inst[(size_t)sg.inst];
+        const cc_plan* P = I.in.plan;
+        const cc_graph* G = I.in.graph;
+        double* root_out = I.in.vertex_dev ? I.in.vertex_dev : (double*)(ws + I.root_off);
+        cc::SegDesc& D = B->seg_host[q];
+        D = cc::SegDesc{};
+        D.S = step_params(P, G, P->splits[(size_t)sg.split], I.in.colours_dev, (double*)(ws + I.arena_off),
+                          pad32(G->n), (double*)(ws + I.partial_off), root_out);
+        D.item_start = item;
+        D.n_items = sg.n_items;
+        D.phase = sg.phase;
+        D.ndep = sg.ndep;
+        for (int d = 0; d < sg.ndep; ++d) {
+            D.dep[d] = sg.dep[d];
+            D.need[d] = (uint32_t)B->segs[(size_t)sg.dep[d]].n_items;
+        }
+        item += sg.n_items;
+    }
+    for (size_t i = 0; i < B->inst.size(); ++i) {
+        const cc_batch::Inst& I = B->inst[i];
+        cc::ReduceDesc& R = B->rd_host[i];
+        R.x = I.in.vertex_dev ? I.in.vertex_dev : (const double*)(ws + I.root_off);
+        R.n = I.in.graph->n;
+        R.out = I.in.X_dev;
+        R.partial = (double*)(ws + I.red_off);
+    }
+    hipError_t e = hipSuccess;
+    if (!B->segs.empty())
+        e = hipMemcpyAsync(seg_dev, B->seg_host.data(), B->seg_host.size() * sizeof(cc::SegDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(rd_dev, B->rd_host.data(), B->rd_host.size() * sizeof(cc::ReduceDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = cc::launch_fill_u32(done, (int64_t)std::max<size_t>(B->segs.size(), 1), 0u, st);
+    if (e == hipSuccess) e = cc::launch_fill_u32(B->err_dev, 1, 0u, st);
+    // instances without splits (k = 1) or without vertices
+    for (size_t i = 0; e == hipSuccess && i < B->inst.size(); ++i) {
+        const cc_batch::Inst& I = B->inst[i];
+        if (I.in.graph->n > 0 && I.in.plan->splits.empty())
+            e = cc::launch_fill_f64(const_cast<double*>(B->rd_host[i].x), I.in.graph->n, 1.0, st);
+    }
+    const int64_t total = B->level_start.back();
+    if (e == hipSuccess && total > 0) {
+        if (B->flags & CC_BATCH_LEVELS) {
+            for (size_t l = 0; e == hipSuccess && l + 1 < B->level_start.size(); ++l)
+                e = cc::launch_batch(seg_dev, (int)B->segs.size(), B->level_start[l], B->level_start[l + 1], B->J,
+                                     B->lds_wave, false, done, B->err_dev, B->n_cu, 1, st);
+        } else {
+            e = cc::launch_batch(seg_dev, (int)B->segs.size(), 0, total, B->J, B->lds_wave, true, done, B->err_dev,
+                                 B->n_cu, (int)((B->flags >> 8) & 0xFFu), st);
+        }
+    }
+    for (size_t i = 0; e == hipSuccess && i < B->inst.size(); ++i)
+        if (B->inst[i].in.graph->n == 0) e = cc::launch_fill_f64(B->inst[i].in.X_dev, 1, 0.0, st);
+    if (e == hipSuccess) e = cc::launch_reduce_batch(rd_dev, (int)B->inst.size(), B->max_red_blocks, st);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return CC_OK;
+}
+
+cc_status cc_batch_check(cc_batch* B, void* stream) {
+    if (!B) return fail(CC_EINVAL, "NULL batch");
+    if (!B->err_dev) return CC_OK;
+    unsigned h = 0;
+    hipError_t e = hipMemcpyAsync(&h, B->err_dev, sizeof(unsigned), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "batch check");
+    if (h) return fail(CC_EINTERNAL, "a dependency wait in the persistent batch launch gave up");
+    return CC_OK;
+}
+
+void cc_batch_destroy(cc_batch* B) { delete B; }
 
 static long double scale_factor(const cc_plan* P) {
     long double s = 1.0L;

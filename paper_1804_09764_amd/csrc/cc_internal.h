@@ -87,8 +87,8 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
 
 int pad_stride(int W);
 
-// arguments of one split launch (host side)
-struct StepParamsHost {
+// Arguments of one split over one graph and one colouring (shared by host and device code).
+struct StepParams {
     const int64_t* row_ptr;
     const int32_t* col;
     const uint8_t* colour;
@@ -97,16 +97,42 @@ struct StepParamsHost {
     const ChunkItem* chunks;
     const HubItem* hubs;
     int64_t n_light, n_ranges, n_chunks, n_hubs;
-    const double* P;
-    const double* A;
-    double* O;
-    double* partial;
+    const double* P;             // passive table (p >= 2)
+    const double* A;             // active table (a >= 2)
+    double* O;                   // output table, or the per-vertex root counts
+    double* partial;             // chunk partial rows
     const uint16_t* fold;
     const uint32_t* split;
     int64_t pstride, astride, ostride, nstride;
     int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
+    int lds_wave;       // doubles of LDS per wavefront
+    int a_off;          // offset of the staged active row inside the wavefront's LDS slice
+    int waves_per_block;
     int cols_per_lane;  // 0 = choose from Wp
-    int n_cu;
+};
+
+// LDS layout of one split: N row (padded), then the active row when a >= 2
+inline int split_a_off(int Nw) { return pad_stride(Nw); }
+inline int split_lds_wave(int Nw, int Wa, int a) { return pad_stride(Nw) + (a >= 2 ? pad_stride(Wa) : 0); }
+
+// One segment of a batched launch: all work items of one phase of one split of one instance.
+// phase 0 = the split's tasks (chunks + light ranges), phase 1 = its cut-row finishes.
+struct SegDesc {
+    StepParams S;
+    int64_t item_start;  // first global item of the segment
+    int64_t n_items;
+    int32_t phase;
+    int32_t ndep;
+    int32_t dep[2];      // segments that must be complete first
+    uint32_t need[2];    // their item counts
+};
+
+// per-instance root reduction of a batch
+struct ReduceDesc {
+    const double* x;
+    int64_t n;
+    double* out;
+    double* partial;  // reduce_blocks_for(n) slots
 };
 
 }  // namespace cc
@@ -122,8 +148,12 @@ hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* ou
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                            unsigned* flags, hipStream_t st);
 // mid (optional) is recorded between the gather kernel and the cut-row finish kernel
-hipError_t launch_split(const StepParamsHost& h, hipStream_t st, hipEvent_t mid);
-size_t split_lds_bytes(int Nw, int Wa, int a);
+hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid);
+// batched launch over segments [seg_lo, seg_hi) (items item_lo..item_hi); wait = honour dependencies
+hipError_t launch_batch(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J, int lds_wave,
+                        bool wait, unsigned* done, unsigned* err, int n_cu, int share, hipStream_t st);
+hipError_t launch_reduce_batch(const ReduceDesc* rd_dev, int n_inst, int max_blocks, hipStream_t st);
+int pick_J(int Wp, int want);
 }  // namespace cc
 
 struct cc_graph {
@@ -139,4 +169,26 @@ struct cc_graph {
     int32_t cols_per_lane = 0;
     int device = 0;
     int n_cu = 0;
+};
+
+struct cc_batch {
+    struct Inst {
+        cc_instance in;
+        size_t arena_off, partial_off, root_off, red_off;
+    };
+    struct Seg {
+        int inst, split, phase, level;
+        int64_t n_items;
+        int dep[2];
+        int ndep;
+    };
+    std::vector<Inst> inst;
+    std::vector<Seg> segs;             // in launch order (by level)
+    std::vector<int64_t> level_start;  // item index where each level starts, plus the total
+    std::vector<cc::SegDesc> seg_host;
+    std::vector<cc::ReduceDesc> rd_host;
+    size_t done_off = 0, err_off = 0, seg_off = 0, rd_off = 0, total = 0;
+    int J = 1, lds_wave = 0, max_red_blocks = 1, n_cu = 0;
+    uint32_t flags = 0;
+    unsigned* err_dev = nullptr;
 };

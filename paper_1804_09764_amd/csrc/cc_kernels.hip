@@ -28,28 +28,6 @@
 
 namespace cc {
 
-struct StepParams {
-    const int64_t* row_ptr;
-    const int32_t* col;
-    const uint8_t* colour;
-    const int32_t* light;
-    const int32_t* light_start;
-    const ChunkItem* chunks;
-    const HubItem* hubs;
-    int64_t n_light, n_ranges, n_chunks, n_hubs;
-    const double* P;
-    const double* A;
-    double* O;
-    double* partial;
-    const uint16_t* fold;
-    const uint32_t* split;
-    int64_t pstride, astride, ostride, nstride;
-    int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
-    int lds_wave;   // doubles of LDS per wavefront
-    int a_off;      // offset of the staged active row inside the wavefront's LDS slice
-    int waves_per_block;
-};
-
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
@@ -261,6 +239,44 @@ __device__ __forceinline__ void light_row(const StepParams& S, int v, double* N,
     wave_sync_lds();
 }
 
+// task t of a split: a chunk of a cut row (partial N row to scratch) or a range of light rows
+template <int J>
+__device__ __forceinline__ void do_task(const StepParams& S, int64_t t, double* N, double* Ash, int lane) {
+    if (t < S.n_chunks) {
+        const ChunkItem ch = S.chunks[t];
+        const int v = __builtin_amdgcn_readfirstlane(ch.v);
+        const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
+        for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
+        wave_sync_lds();
+        if (cv < S.k) {
+            if (S.p == 1) count_colours(S, ch.beg, ch.beg + ch.len, cv, N, lane);
+            else gather_fold<J>(S, ch.beg, ch.beg + ch.len, cv, N, lane);
+        }
+        wave_sync_lds();
+        double* prow = S.partial + t * S.nstride;
+        for (int r = lane; r < S.Nw; r += kWave) prow[r] = N[r];
+        wave_sync_lds();
+    } else {
+        const int64_t r = t - S.n_chunks;
+        const int i0 = S.light_start[r], i1 = S.light_start[r + 1];
+        for (int i = i0; i < i1; ++i) light_row<J>(S, S.light[i], N, Ash, lane);
+    }
+}
+
+// cut row t of a split: add its chunk partials in chunk order, then combine
+__device__ __forceinline__ void do_hub(const StepParams& S, int64_t t, double* N, double* Ash, int lane) {
+    const HubItem h = S.hubs[t];
+    for (int r = lane; r < S.Nw; r += kWave) {
+        double sum = 0.0;
+        const double* pp = S.partial + h.first_chunk * S.nstride + r;
+        for (int c = 0; c < h.n_chunks; ++c) sum += pp[(int64_t)c * S.nstride];
+        N[r] = sum;
+    }
+    wave_sync_lds();
+    combine_store(S, h.v, N, Ash, lane);
+    wave_sync_lds();
+}
+
 // Tasks (chunks of cut rows first, then ranges of light rows, all of about `chunk` entries) are
 // dealt to the persistent wavefronts round-robin: no shared counter, one fixed owner per task.
 template <int J>
@@ -272,30 +288,10 @@ __global__ __launch_bounds__(256) void k_split(StepParams S) {
     double* Ash = N + S.a_off;
     const int64_t n_tasks = S.n_chunks + S.n_ranges;
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves) {
-        if (t < S.n_chunks) {
-            const ChunkItem ch = S.chunks[t];
-            const int v = __builtin_amdgcn_readfirstlane(ch.v);
-            const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
-            for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
-            wave_sync_lds();
-            if (cv < S.k) {
-                if (S.p == 1) count_colours(S, ch.beg, ch.beg + ch.len, cv, N, lane);
-                else gather_fold<J>(S, ch.beg, ch.beg + ch.len, cv, N, lane);
-            }
-            wave_sync_lds();
-            double* prow = S.partial + t * S.nstride;
-            for (int r = lane; r < S.Nw; r += kWave) prow[r] = N[r];
-            wave_sync_lds();
-        } else {
-            const int64_t r = t - S.n_chunks;
-            const int i0 = S.light_start[r], i1 = S.light_start[r + 1];
-            for (int i = i0; i < i1; ++i) light_row<J>(S, S.light[i], N, Ash, lane);
-        }
-    }
+    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves)
+        do_task<J>(S, t, N, Ash, lane);
 }
 
-// rows that were cut: add the chunk partials in chunk order, then combine
 __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
     extern __shared__ double lds[];
     const int lane = lane_id();
@@ -303,18 +299,119 @@ __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
     double* N = lds + (int64_t)wib * S.lds_wave;
     double* Ash = N + S.a_off;
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves) {
-        const HubItem h = S.hubs[t];
-        for (int r = lane; r < S.Nw; r += kWave) {
-            double sum = 0.0;
-            const double* pp = S.partial + h.first_chunk * S.nstride + r;
-            for (int c = 0; c < h.n_chunks; ++c) sum += pp[(int64_t)c * S.nstride];
-            N[r] = sum;
+    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves)
+        do_hub(S, t, N, Ash, lane);
+}
+
+// ---------------------------------------------------------------------------------------------
+// batched launch: many (instance, split) segments in one persistent kernel
+// ---------------------------------------------------------------------------------------------
+
+constexpr unsigned kWaitLimit = 20u * 1000u * 1000u;  // polls (each about a microsecond) before giving up
+
+// wavefront-completed items of a segment become visible to other workgroups (release)
+__device__ __forceinline__ void publish(unsigned* done, int seg, unsigned cnt, int lane) {
+    if (seg < 0 || cnt == 0) return;
+    __threadfence();
+    if (lane == 0) __hip_atomic_fetch_add(done + seg, cnt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// wait until the segments this one reads are complete (acquire); gives up after kWaitLimit polls
+__device__ __forceinline__ void wait_deps(const SegDesc& D, const unsigned* done, unsigned* err, int lane) {
+    for (int i = 0; i < D.ndep; ++i) {
+        if (lane == 0) {
+            unsigned polls = 0;
+            while (__hip_atomic_load(done + D.dep[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < D.need[i]) {
+                __builtin_amdgcn_s_sleep(16);
+                if (++polls > kWaitLimit) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+            }
         }
-        wave_sync_lds();
-        combine_store(S, h.v, N, Ash, lane);
-        wave_sync_lds();
     }
+    __threadfence();
+}
+
+// Items [item_lo, item_hi) of the segment list are dealt round-robin to the persistent wavefronts.
+// Segments are ordered by dependency level, so every item depends only on items with smaller
+// indices; a wavefront publishes what it completed of a segment before it waits on anything, so
+// the smallest unfinished item can always run and the launch drains.
+template <int J>
+__global__ __launch_bounds__(256) void k_batch(const SegDesc* __restrict__ segs, int n_segs, int64_t item_lo,
+                                               int64_t item_hi, int lds_wave, int wpb, int wait, unsigned* done,
+                                               unsigned* err) {
+    extern __shared__ double lds[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    double* N = lds + (int64_t)wib * lds_wave;
+    const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    int cur = -1, verified = -1;
+    unsigned pending = 0;
+    for (int64_t t = item_lo + (int64_t)blockIdx.x * wpb + wib; t < item_hi; t += n_waves) {
+        int lo = 0, hi = n_segs;  // last segment with item_start <= t
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (segs[mid].item_start <= t) lo = mid;
+            else hi = mid;
+        }
+        const int seg = __builtin_amdgcn_readfirstlane(lo);
+        if (seg != cur) {
+            publish(done, cur, pending, lane);
+            pending = 0;
+            cur = seg;
+        }
+        const SegDesc& D = segs[seg];
+        if (wait && seg != verified) {
+            wait_deps(D, done, err, lane);
+            verified = seg;
+        }
+        const int64_t local = t - D.item_start;
+        double* Ash = N + D.S.a_off;
+        if (D.phase == 0) do_task<J>(D.S, local, N, Ash, lane);
+        else do_hub(D.S, local, N, Ash, lane);
+        ++pending;
+    }
+    publish(done, cur, pending, lane);
+}
+
+// per-instance root sums, blocks laid out exactly as launch_reduce does for one instance
+__global__ __launch_bounds__(256) void k_reduce_batch_blocks(const ReduceDesc* rd) {
+    __shared__ double sh[256];
+    const ReduceDesc R = rd[blockIdx.y];
+    int64_t blocks = (R.n + 65535) / 65536;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    if ((int64_t)blockIdx.x >= blocks) return;
+    const int64_t per = (R.n + blocks - 1) / blocks;
+    const int64_t lo = blockIdx.x * per;
+    const int64_t hi = lo + per < R.n ? lo + per : R.n;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += R.x[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) R.partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_batch_final(const ReduceDesc* rd) {
+    __shared__ double sh[256];
+    const ReduceDesc R = rd[blockIdx.x];
+    int64_t blocks = (R.n + 65535) / 65536;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < blocks; i += 256) s += R.partial[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) R.out[0] = sh[0];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -465,36 +562,29 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n
 }
 
 // passive-row doubles per lane per pass
-static int pick_J(int Wp, int want) {
+int pick_J(int Wp, int want) {
     if (want == 1 || want == 2 || want == 4 || want == 8) return want;
     if (Wp <= 64) return 1;
     if (Wp <= 128) return 2;
     return 4;
 }
 
-hipError_t launch_split(const StepParamsHost& h, hipStream_t st, hipEvent_t mid) {
-    StepParams S;
-    S.row_ptr = h.row_ptr; S.col = h.col; S.colour = h.colour;
-    S.light = h.light; S.light_start = h.light_start; S.chunks = h.chunks; S.hubs = h.hubs;
-    S.n_light = h.n_light; S.n_ranges = h.n_ranges; S.n_chunks = h.n_chunks; S.n_hubs = h.n_hubs;
-    S.P = h.P; S.A = h.A; S.O = h.O; S.partial = h.partial;
-    S.fold = h.fold; S.split = h.split;
-    S.pstride = h.pstride; S.astride = h.astride; S.ostride = h.ostride; S.nstride = h.nstride;
-    S.k = h.k; S.s = h.s; S.a = h.a; S.p = h.p;
-    S.Wa = h.Wa; S.Wp = h.Wp; S.Ws = h.Ws; S.Nw = h.Nw; S.npairs = h.npairs;
-    const int n_pad = pad_stride(h.Nw);
-    const int a_pad = (h.a >= 2) ? pad_stride(h.Wa) : 0;
-    S.a_off = n_pad;
-    S.lds_wave = n_pad + a_pad;
-    // up to four wavefronts per workgroup, fewer when one wavefront's slice is large
-    int waves_per_block = 4;
-    while (waves_per_block > 1 && (size_t)S.lds_wave * waves_per_block * sizeof(double) > 64 * 1024)
-        waves_per_block >>= 1;
+// up to four wavefronts per workgroup, fewer when one wavefront's LDS slice is large
+static int waves_for_lds(int lds_wave) {
+    int w = 4;
+    while (w > 1 && (size_t)lds_wave * w * sizeof(double) > 64 * 1024) w >>= 1;
+    return w;
+}
+
+hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) {
+    S.a_off = split_a_off(S.Nw);
+    S.lds_wave = split_lds_wave(S.Nw, S.Wa, S.a);
     if ((size_t)S.lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
+    const int waves_per_block = waves_for_lds(S.lds_wave);
     const int threads = waves_per_block * kWave;
     S.waves_per_block = waves_per_block;
     const size_t lds = (size_t)S.lds_wave * waves_per_block * sizeof(double);
-    int J = (h.p >= 2) ? pick_J(h.Wp, h.cols_per_lane) : 1;
+    const int J = (S.p >= 2) ? pick_J(S.Wp, S.cols_per_lane) : 1;
     const void* fn = nullptr;
     switch (J) {
         case 1: fn = (const void*)k_split<1>; break;
@@ -506,8 +596,8 @@ hipError_t launch_split(const StepParamsHost& h, hipStream_t st, hipEvent_t mid)
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
     if (err != hipSuccess) return err;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const int64_t total = h.n_chunks + h.n_ranges;
-    int64_t blocks = (int64_t)per_cu * h.n_cu;
+    const int64_t total = S.n_chunks + S.n_ranges;
+    int64_t blocks = (int64_t)per_cu * n_cu;
     const int64_t need = (total + waves_per_block - 1) / waves_per_block;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
@@ -525,13 +615,13 @@ hipError_t launch_split(const StepParamsHost& h, hipStream_t st, hipEvent_t mid)
         err = hipEventRecord(mid, st);
         if (err != hipSuccess) return err;
     }
-    if (h.n_hubs > 0) {
+    if (S.n_hubs > 0) {
         int per_cu2 = 0;
         err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_hub_finish, threads, lds);
         if (err != hipSuccess) return err;
         if (per_cu2 < 1) return hipErrorInvalidConfiguration;
-        int64_t b2 = (int64_t)per_cu2 * h.n_cu;
-        const int64_t need2 = (h.n_hubs + waves_per_block - 1) / waves_per_block;
+        int64_t b2 = (int64_t)per_cu2 * n_cu;
+        const int64_t need2 = (S.n_hubs + waves_per_block - 1) / waves_per_block;
         if (b2 > need2) b2 = need2;
         hipLaunchKernelGGL(k_hub_finish, dim3((unsigned)b2), dim3(threads), lds, st, S);
         err = hipGetLastError();
@@ -539,10 +629,44 @@ hipError_t launch_split(const StepParamsHost& h, hipStream_t st, hipEvent_t mid)
     return err;
 }
 
-size_t split_lds_bytes(int Nw, int Wa, int a) {
-    const int n_pad = pad_stride(Nw);
-    const int a_pad = (a >= 2) ? pad_stride(Wa) : 0;
-    return (size_t)(n_pad + a_pad) * sizeof(double);
+hipError_t launch_batch(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J, int lds_wave,
+                        bool wait, unsigned* done, unsigned* err, int n_cu, int share, hipStream_t st) {
+    if (item_hi <= item_lo) return hipSuccess;
+    if ((size_t)lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
+    const int wpb = waves_for_lds(lds_wave);
+    const int threads = wpb * kWave;
+    const size_t lds = (size_t)lds_wave * wpb * sizeof(double);
+    const void* fn = nullptr;
+    switch (J) {
+        case 1: fn = (const void*)k_batch<1>; break;
+        case 2: fn = (const void*)k_batch<2>; break;
+        case 4: fn = (const void*)k_batch<4>; break;
+        default: fn = (const void*)k_batch<8>; break;
+    }
+    int per_cu = 0;
+    hipError_t err2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    if (err2 != hipSuccess) return err2;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    // every workgroup must be resident at once (the dependency waits rely on it)
+    int64_t blocks = (int64_t)per_cu * n_cu / (share > 1 ? share : 1);
+    if (blocks < 1) blocks = 1;
+    const int64_t need = (item_hi - item_lo + wpb - 1) / wpb;
+    if (blocks > need) blocks = need;
+    const int w = wait ? 1 : 0;
+    switch (J) {
+        case 1: hipLaunchKernelGGL(k_batch<1>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
+        case 2: hipLaunchKernelGGL(k_batch<2>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
+        case 4: hipLaunchKernelGGL(k_batch<4>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
+        default: hipLaunchKernelGGL(k_batch<8>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const ReduceDesc* rd_dev, int n_inst, int max_blocks, hipStream_t st) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_batch_blocks, dim3((unsigned)max_blocks, (unsigned)n_inst), dim3(256), 0, st, rd_dev);
+    hipLaunchKernelGGL(k_reduce_batch_final, dim3((unsigned)n_inst), dim3(256), 0, st, rd_dev);
+    return hipGetLastError();
 }
 
 }  // namespace cc
