@@ -41,7 +41,7 @@ WORKLOADS = {
     "rmat23-ef256-u12": dict(scale=23, ef=256, gseed=3, k=12, tseed=12, B=4, trust=True),
     "rmat20-ef16-u15": dict(scale=20, ef=16, gseed=1, k=15, tseed=15, B=1, trust=False),
 }
-DEFAULT_WORKLOAD = "rmat20-ef16-u12"
+DEFAULT_WORKLOAD = "rmat23-ef256-u12"
 
 
 def kernel_hash() -> str:
@@ -71,8 +71,11 @@ def split_bytes(k, s, a, p, n, nnz):
 
 
 def loaded_bytes(k, s, a, p, n, nnz):
-    """Bytes the wavefronts request (cache hits included): one passive row per CSR entry whose
-    neighbour colour differs from the row's (expected fraction (k-1)/k), plus the compulsory rest."""
+    """Algorithmic bytes of one split launch: what its loads and stores must move through the
+    memory hierarchy. Per CSR entry: the column (4 B), the neighbour's colour (1 B) and, for the
+    expected fraction (k-1)/k of neighbours whose colour differs from the row's, the neighbour's
+    colour-anchored passive row (8 C(k-1, p-1) B, none when p = 1); per vertex: its row offsets,
+    colour, active row (a >= 2) and output row."""
     Wp, Wa, Ws = widths(k, s, a, p)
     b = 5 * nnz + 8 * (n + 1) + n + 8 * n * Ws + (8 * n * Wa if a >= 2 else 0)
     if p >= 2:
@@ -96,9 +99,11 @@ def cpu_baseline(row_ptr, col, T, target_s=15.0):
     """The oracle, timed on a bounded sample of the same workload.
 
     For every split of the reference partition, oracle.step (Eq. 1 as written: per vertex, per
-    colour set, neighbours then splits) runs over a uniform random sample of centre vertices with
-    random integer input tables; CSEU are counted exactly as on the GPU (deg(v) * w(p) per sampled
-    vertex). The sample size is doubled until the sample takes about `target_s` seconds.
+    colour set, neighbours then splits) runs over a uniform random sample of centre vertices of the
+    benchmark graph, with their true neighbour lists; the neighbours' passive rows come from a
+    bounded table of random integers (row = neighbour id mod 65536) and the active rows are random
+    integers. CSEU are counted exactly as on the GPU (deg(v) * w(p) per sampled vertex). The sample
+    is doubled until it takes about `target_s` seconds.
     """
     import numpy as np
 
@@ -110,34 +115,36 @@ def cpu_baseline(row_ptr, col, T, target_s=15.0):
     n = len(row_ptr) - 1
     rng = np.random.default_rng(2024)
     deg = np.diff(row_ptr)
+    rows = 65536
+    tables = {p: rng.integers(0, 4, size=(rows, math.comb(k, p))).astype(np.float64)
+              for p in sorted({p for _, _, p in ref.splits})}
 
     def run(m):
         vs = np.sort(rng.choice(n, size=m, replace=False))
-        starts = row_ptr[vs]
         lens = deg[vs]
         nbr_ptr = np.zeros(m + 1, dtype=np.int64)
         nbr_ptr[1:] = np.cumsum(lens)
-        idx = np.concatenate([col[s:s + l] for s, l in zip(starts, lens)]) if m else np.zeros(0, np.int32)
-        uniq, inv = np.unique(idx, return_inverse=True)
+        idx = (np.concatenate([col[row_ptr[v]:row_ptr[v + 1]] for v in vs]) if m else np.zeros(0, np.int32))
+        idx = (idx % rows).astype(np.int32)
         units = 0
         secs = 0.0
         for (s, a, p) in ref.splits:
             act = rng.integers(0, 4, size=(m, math.comb(k, a))).astype(np.float64)
-            pas = rng.integers(0, 4, size=(len(uniq), math.comb(k, p))).astype(np.float64)
             t0 = time.perf_counter()
-            oracle.step(k, s, a, nbr_ptr, inv.astype(np.int32), act, pas)
+            oracle.step(k, s, a, nbr_ptr, idx, act, tables[p])
             secs += time.perf_counter() - t0
             units += int(lens.sum()) * (math.comb(k, p) if p >= 2 else 1)
         return units, secs, m
 
-    m = 64
+    m = 16
     units, secs, m = run(m)
     while secs < target_s / 2 and m < n:
         m = min(n, int(m * max(2.0, min(8.0, target_s / max(secs, 1e-3)))))
         units, secs, m = run(m)
     return {"value": units / secs, "unit": "CSEU/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{m} uniformly sampled centre vertices, every split of the reference partition, "
-                      f"random integer tables; {units:.3e} CSEU in {secs:.1f} s"}
+            "sample": f"{m} uniformly sampled centre vertices with their neighbour lists, every split of the "
+                      f"reference partition, random integer tables (passive rows: 65536, indexed by neighbour id "
+                      f"mod 65536); {units:.3e} CSEU in {secs:.1f} s"}
 
 
 def bench(args):
@@ -151,14 +158,12 @@ def bench(args):
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     t0 = time.time()
-    row_ptr, col = inputs.rmat_graph(W["scale"], W["ef"], W["gseed"], threads=args.gen_threads)
-    n, nnz = len(row_ptr) - 1, len(col)
-    print(f"[bench] graph scale={W['scale']} ef={W['ef']} n={n} nnz={nnz} built in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    rp_d, col_d = inputs.rmat_graph_gpu(W["scale"], W["ef"], W["gseed"], device=dev)
+    n, nnz = rp_d.numel() - 1, col_d.numel()
+    print(f"[bench] graph scale={W['scale']} ef={W['ef']} n={n} nnz={nnz} built on the GPU in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     T = inputs.pruefer_tree(W["k"], W["tseed"])
     k, B = W["k"], W["B"]
-    rp_d = torch.from_numpy(row_ptr).to(dev)
-    col_d = torch.from_numpy(col).to(dev)
     G = cc.Graph(rp_d, col_d, hub_threshold=args.hub_threshold, chunk=args.chunk, trust=W["trust"])
     P = cc.Plan(T)
     units_per_edge = P.info.units_per_edge
@@ -192,7 +197,7 @@ def bench(args):
     dom = int(np.argmax(gather_ms))
     s, a, p = P.splits[dom]
     avg_ms = gather_ms[dom] / max(1, launches[dom])
-    alg = split_bytes(k, s, a, p, n, nnz)
+    alg = loaded_bytes(k, s, a, p, n, nnz)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     traffic = load_traffic(args.workload, dom)
     per_split = [{"s": S, "a": A, "p": Pp, "gather_ms": round(float(g) / max(1, c), 4),
@@ -221,11 +226,13 @@ def bench(args):
                      "kernel": f"k_split split {dom} (s={s}, a={a}, p={p})",
                      "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg,
-                     "loaded_GBps": loaded_bytes(k, s, a, p, n, nnz) / (avg_ms * 1e-3) / 1e9},
+                     "compulsory_bytes_per_launch": split_bytes(k, s, a, p, n, nnz),
+                     "traffic_GBps": (traffic / (avg_ms * 1e-3)) if traffic else None},
         "splits": per_split,
         "X_last": [float(x) for x in Xh],
     }
     if not args.no_cpu_baseline:
+        row_ptr, col = rp_d.cpu().numpy(), col_d.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(row_ptr, col, T, target_s=args.cpu_seconds)
     return out
 
@@ -283,13 +290,12 @@ def summarize_pmc(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=777)
     ap.add_argument("--hub-threshold", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--gen-threads", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0,

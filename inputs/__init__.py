@@ -30,15 +30,90 @@ _H = np.uint64(0xD1B54A32D192ED03)
 RMAT_ABC = (0.57, 0.19, 0.19)
 
 
+_GPU_LIB_PATH = os.path.join(_HERE, "libgen_gpu.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile inputs/gen.c into inputs/libgen.so (gcc, OpenMP)."""
+    """Compile inputs/gen.c into inputs/libgen.so (gcc, OpenMP) and inputs/gen_gpu.hip into
+    inputs/libgen_gpu.so (hipcc, gfx950)."""
     src = os.path.join(_HERE, "gen.c")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, src, "-lm"])
         os.replace(tmp, _LIB_PATH)
+    gsrc = os.path.join(_HERE, "gen_gpu.hip")
+    if force or not os.path.exists(_GPU_LIB_PATH) or os.path.getmtime(_GPU_LIB_PATH) < os.path.getmtime(gsrc):
+        tmp = _GPU_LIB_PATH + ".tmp"
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-o", tmp, gsrc], stderr=subprocess.DEVNULL)
+        os.replace(tmp, _GPU_LIB_PATH)
     return _LIB_PATH
+
+
+@lru_cache(maxsize=1)
+def _gpu_lib():
+    if not os.path.exists(_GPU_LIB_PATH):
+        raise RuntimeError(f"{_GPU_LIB_PATH} is not built; run inputs.build()")
+    L = ctypes.CDLL(_GPU_LIB_PATH)
+    P, U64, I64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64
+    L.gen_gpu_count.argtypes = [ctypes.c_int, U64, P, U64, P, P]
+    L.gen_gpu_scatter.argtypes = [ctypes.c_int, U64, P, U64, P, P, P]
+    L.gen_gpu_sort_small.argtypes = [P, P, I64, P, P, P]
+    L.gen_gpu_sort_large.argtypes = [P, P, ctypes.c_int, P, P, I64, P, P]
+    L.gen_gpu_compact.argtypes = [P, P, P, I64, P, P]
+    return L
+
+
+def rmat_graph_gpu(scale: int, edge_factor: int, seed: int, abc=RMAT_ABC, device="cuda",
+                   bitmap_budget: int = 4 << 30):
+    """The same R-MAT graph as rmat_graph(), built on the GPU; returns (row_ptr, col) torch tensors
+    (int64, int32) on `device`."""
+    import torch
+    L = _gpu_lib()
+    dev = torch.device(device)
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    k8 = np.array(rmat_params(scale, *abc, seed), dtype=np.uint64)
+    n = 1 << scale
+    E = edge_factor << scale
+
+    def chk(rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what}: hip error {rc}")
+
+    deg = torch.zeros(n, dtype=torch.int32, device=dev)
+    chk(L.gen_gpu_count(scale, E, k8.ctypes.data, seed, deg.data_ptr(), st), "count")
+    off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    off[1:] = torch.cumsum(deg.to(torch.int64), 0)
+    cursor = off[:-1].clone()
+    raw_n = int(off[-1].item())
+    raw = torch.empty(max(raw_n, 1), dtype=torch.int32, device=dev)
+    chk(L.gen_gpu_scatter(scale, E, k8.ctypes.data, seed, cursor.data_ptr(), raw.data_ptr(), st), "scatter")
+    del cursor
+    uniq = torch.zeros(n, dtype=torch.int32, device=dev)
+    small = torch.nonzero((deg > 0) & (deg <= 4096)).view(-1).to(torch.int32)
+    large = torch.nonzero(deg > 4096).view(-1).to(torch.int32)
+    chk(L.gen_gpu_sort_small(off.data_ptr(), small.data_ptr(), small.numel(), raw.data_ptr(), uniq.data_ptr(), st),
+        "sort small rows")
+    words = (n + 31) // 32
+    group = max(1, min(4096, bitmap_budget // (words * 4), large.numel()))
+    if large.numel():
+        bitmaps = torch.empty(group * words, dtype=torch.int32, device=dev)
+        for g0 in range(0, large.numel(), group):
+            rows = large[g0:g0 + group].contiguous()
+            bitmaps.zero_()
+            chk(L.gen_gpu_sort_large(off.data_ptr(), rows.data_ptr(), rows.numel(), raw.data_ptr(),
+                                     bitmaps.data_ptr(), words, uniq.data_ptr(), st), "sort large rows")
+        del bitmaps
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    row_ptr[1:] = torch.cumsum(uniq.to(torch.int64), 0)
+    col = torch.empty(max(int(row_ptr[-1].item()), 1), dtype=torch.int32, device=dev)
+    chk(L.gen_gpu_compact(off.data_ptr(), row_ptr.data_ptr(), raw.data_ptr(), n, col.data_ptr(), st), "compact")
+    nnz = int(row_ptr[-1].item())
+    torch.cuda.synchronize(dev)
+    del raw
+    return row_ptr, col[:nnz]
 
 
 @lru_cache(maxsize=1)

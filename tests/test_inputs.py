@@ -63,3 +63,13 @@ def test_pruefer_is_tree(k):
         ru, rv = find(int(u)), find(int(v))
         assert ru != rv
         parent[ru] = rv
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("scale,ef,seed", [(6, 4, 1), (12, 16, 2), (15, 64, 3), (16, 8, 4)])
+def test_rmat_gpu_builder_equals_cpu(scale, ef, seed):
+    import torch
+    rp_g, col_g = inputs.rmat_graph_gpu(scale, ef, seed, device="cuda:0")
+    rp, cl = inputs.rmat_graph(scale, ef, seed)
+    np.testing.assert_array_equal(rp_g.cpu().numpy(), rp)
+    np.testing.assert_array_equal(col_g.cpu().numpy(), cl)
