@@ -234,7 +234,71 @@ def bench(args):
     if not args.no_cpu_baseline:
         row_ptr, col = rp_d.cpu().numpy(), col_d.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(row_ptr, col, T, target_s=args.cpu_seconds)
+        del row_ptr, col
+    del G, ws, rp_d, col_d
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] plain vs batched", file=sys.stderr, flush=True)
+        out["batched"] = batched_vs_plain(args)
     return out
+
+
+def batched_vs_plain(args, reps: int = 2):
+    """Plain vs batched on the batched configuration: R-MAT scale 18 (edge factor 16, seed 2), all
+    11 trees with 7 vertices x 64 colourings. Plain = one cc_count call per tree over the 64
+    colourings (colourings and splits run one after another); batched = the 704 instances in one
+    persistent launch (and, for reference, one launch per dependency level). Results must agree
+    bit for bit."""
+    import torch
+
+    import inputs
+    import paper_1804_09764_amd as cc
+
+    dev = torch.device("cuda:0")
+    rp_d, col_d = inputs.rmat_graph_gpu(18, 16, 2, device=dev)
+    n, nnz = rp_d.numel() - 1, col_d.numel()
+    G = cc.Graph(rp_d, col_d)
+    trees = inputs.all_trees(7)
+    plans = [cc.Plan(T) for T in trees]
+    B = 64
+    C = cc.colour(G, 7, seed=args.seed, first_iter=0, B=B)
+    units = float(nnz) * sum(p.info.units_per_edge for p in plans) * B
+    ws = cc.Workspace()
+    Xp = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
+
+    def plain():
+        for t, P in enumerate(plans):
+            cc.count(P, G, C, workspace=ws, out=Xp[t])
+
+    Xb = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
+    inst = [(P, G, C[b], Xb[t, b:b + 1], None) for t, P in enumerate(plans) for b in range(B)]
+    persistent = cc.Batch(inst)
+    levels = cc.Batch(inst, levels=True)
+    wsb = cc.Workspace()
+    res = {}
+    for name, fn in (("plain", plain), ("batched", lambda: persistent.run(wsb)), ("levels", lambda: levels.run(wsb))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / reps
+        if name != "plain":
+            if name == "batched":
+                persistent.check()
+            same = bool(torch.equal(Xb, Xp))
+            res[name + "_equal"] = same
+    return {"workload": "rmat18-ef16-trees7x64",
+            "graph": "R-MAT scale 18 edge factor 16 seed 2", "n": n, "nnz": nnz,
+            "templates": "all 11 trees with 7 vertices", "colourings": B, "instances": len(inst),
+            "units": units,
+            "plain": {"value": units / res["plain"], "ms": res["plain"] * 1e3},
+            "batched": {"value": units / res["batched"], "ms": res["batched"] * 1e3,
+                        "equal_to_plain": res["batched_equal"], "launch": "one persistent launch"},
+            "levels": {"value": units / res["levels"], "ms": res["levels"] * 1e3,
+                       "equal_to_plain": res["levels_equal"], "launch": "one launch per dependency level"},
+            "workspace_GB": persistent.workspace_bytes / 1e9}
 
 
 def summarize_pmc(args):
@@ -297,6 +361,7 @@ def main():
     ap.add_argument("--hub-threshold", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the plain-vs-batched comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")

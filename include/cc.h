@@ -200,18 +200,19 @@ typedef struct {
 
 typedef struct cc_batch cc_batch;
 
-#define CC_BATCH_LEVELS 1u  /* one launch per dependency level instead of one persistent launch */
-/* The persistent launch sizes its grid to the device's resident capacity; a batch that may run
- * concurrently with d-1 other persistent batches must take at most 1/d of it, set as
- * CC_BATCH_SHARE(d) (1 <= d <= 255), so that all their workgroups can be resident together. */
+#define CC_BATCH_LEVELS 1u  /* one launch per split level instead of one persistent launch */
+/* The persistent launch sizes its grid to the device's resident capacity; a batch meant to run
+ * next to d-1 other batches on other streams can take 1/d of it, set as CC_BATCH_SHARE(d)
+ * (1 <= d <= 255), leaving room for their workgroups. */
 #define CC_BATCH_SHARE(d) (((uint32_t)(d) & 0xFFu) << 8)
 
 /*
  * Prepare a batch of n_inst instances (host only; the instance array is copied). Every instance
  * computes exactly what cc_count computes for its plan, graph and colouring, bit for bit: the
- * kernels and the per-entry summation order are the same. By default all splits of all instances
- * run in one persistent launch in which work items wait on per-(instance, split) completion
- * counters; CC_BATCH_LEVELS runs one launch per dependency level instead.
+ * kernels and the per-entry summation order are the same. By default the whole batch runs in one
+ * persistent launch in which each workgroup owns whole instances and runs their splits in plan
+ * order (a workgroup barrier between splits; no device-wide synchronisation); CC_BATCH_LEVELS
+ * runs one launch per split level across all instances instead.
  */
 cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flags, cc_batch** out);
 
@@ -225,8 +226,7 @@ cc_status cc_batch_workspace_bytes(const cc_batch* batch, size_t* bytes);
  */
 cc_status cc_batch_run(cc_batch* batch, void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Synchronise `stream` and report whether the last run completed (CC_EINTERNAL if a dependency
- * wait inside the persistent launch gave up). */
+/* Synchronise `stream` and report any device error of the work queued on it (CC_EDEVICE). */
 cc_status cc_batch_check(cc_batch* batch, void* stream);
 
 void cc_batch_destroy(cc_batch* batch);

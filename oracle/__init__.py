@@ -80,11 +80,11 @@ def colour(seed: int, it: int, n: int, k: int) -> np.ndarray:
 
 
 def count(row_ptr, col, colours, tree_edges, root: int = -1, rule: int = 0, per_vertex: bool = False,
-          threads: int = 0):
+          threads: int = 0, longdouble: bool = False):
     """Colourful labelled embeddings X for one colouring (exact below 2^53).
 
-    Returns X as a Python float (long double rounded) and, if asked, the per-vertex counts
-    C(v, T rooted at `root`, all colours) as float64.
+    Returns X as a Python float (long double rounded; the numpy longdouble if `longdouble`) and,
+    if asked, the per-vertex counts C(v, T rooted at `root`, all colours) as float64.
     """
     rp = _c(row_ptr, np.int64)
     cl = _c(col, np.int32)
@@ -98,7 +98,8 @@ def count(row_ptr, col, colours, tree_edges, root: int = -1, rule: int = 0, per_
                           ctypes.byref(X), threads)
     if rc:
         raise ValueError(f"orc_count rc={rc}")
-    return (X.value, pv) if per_vertex else X.value
+    Xv = np.longdouble(X.value) if longdouble else X.value
+    return (Xv, pv) if per_vertex else Xv
 
 
 def count_ld(row_ptr, col, colours, tree_edges, root: int = -1, rule: int = 0, threads: int = 0):

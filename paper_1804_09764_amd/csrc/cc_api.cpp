@@ -547,35 +547,39 @@ cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flag
                 B->lds_wave = std::max(B->lds_wave, cc::split_lds_wave(sp.Nw, sp.Wa, sp.a));
             }
         }
-        // launch order: by level, then instance, split, phase; dependencies renumbered
-        std::vector<int> order(segs.size());
-        for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return segs[(size_t)x].level < segs[(size_t)y].level; });
-        std::vector<int> pos(segs.size());
-        for (size_t q = 0; q < order.size(); ++q) pos[(size_t)order[q]] = (int)q;
-        B->segs.resize(segs.size());
-        int max_level = -1;
-        for (size_t q = 0; q < order.size(); ++q) {
-            cc_batch::Seg sg = segs[(size_t)order[q]];
-            for (int d = 0; d < sg.ndep; ++d) sg.dep[d] = pos[(size_t)sg.dep[d]];
-            B->segs[q] = sg;
-            max_level = std::max(max_level, sg.level);
+        // instance-major order (as built) for the persistent launch; level order for the
+        // level-by-level launches (stable: instance, split, phase within a level)
+        B->segs = segs;
+        B->ranges.assign((size_t)n_inst, cc::SegRange{0, 0});
+        for (size_t q = 0; q < segs.size(); ++q) {
+            cc::SegRange& r = B->ranges[(size_t)segs[q].inst];
+            if (r.count == 0) r.first = (int32_t)q;
+            r.count++;
         }
+        B->level_order.resize(segs.size());
+        for (size_t q = 0; q < segs.size(); ++q) B->level_order[q] = (int)q;
+        std::stable_sort(B->level_order.begin(), B->level_order.end(),
+                         [&](int x, int y) { return segs[(size_t)x].level < segs[(size_t)y].level; });
+        int max_level = -1;
+        for (const auto& sg : segs) max_level = std::max(max_level, sg.level);
         int64_t item = 0;
         B->level_start.assign((size_t)(max_level + 2), 0);
         int lvl = 0;
-        for (size_t q = 0; q < B->segs.size(); ++q) {
-            while (lvl <= B->segs[q].level) B->level_start[(size_t)lvl++] = item;
-            item += B->segs[q].n_items;
+        for (size_t q = 0; q < B->level_order.size(); ++q) {
+            const cc_batch::Seg& sg = segs[(size_t)B->level_order[q]];
+            while (lvl <= sg.level) B->level_start[(size_t)lvl++] = item;
+            item += sg.n_items;
         }
         while (lvl <= max_level + 1) B->level_start[(size_t)lvl++] = item;
         if (B->lds_wave == 0) B->lds_wave = 16;
-        B->done_off = take(std::max<size_t>(B->segs.size(), 1) * sizeof(unsigned));
-        B->err_off = take(sizeof(unsigned));
-        B->seg_off = take(std::max<size_t>(B->segs.size(), 1) * sizeof(cc::SegDesc));
+        const size_t nseg = std::max<size_t>(B->segs.size(), 1);
+        B->seg_off = take(nseg * sizeof(cc::SegDesc));
+        B->seg_level_off = take(nseg * sizeof(cc::SegDesc));
+        B->range_off = take(std::max<size_t>((size_t)n_inst, 1) * sizeof(cc::SegRange));
         B->rd_off = take(std::max<size_t>((size_t)n_inst, 1) * sizeof(cc::ReduceDesc));
         B->total = off;
         B->seg_host.resize(B->segs.size());
+        B->seg_level_host.resize(B->segs.size());
         B->rd_host.resize((size_t)n_inst);
     } catch (const std::bad_alloc&) {
         delete B;
@@ -597,11 +601,10 @@ cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream)
     if (B->inst.empty()) return CC_OK;
     hipStream_t st = (hipStream_t)stream;
     uint8_t* ws = (uint8_t*)ws_dev;
-    unsigned* done = (unsigned*)(ws + B->done_off);
-    B->err_dev = (unsigned*)(ws + B->err_off);
     cc::SegDesc* seg_dev = (cc::SegDesc*)(ws + B->seg_off);
+    cc::SegDesc* seg_level_dev = (cc::SegDesc*)(ws + B->seg_level_off);
+    cc::SegRange* range_dev = (cc::SegRange*)(ws + B->range_off);
     cc::ReduceDesc* rd_dev = (cc::ReduceDesc*)(ws + B->rd_off);
-    int64_t item = 0;
     for (size_t q = 0; q < B->segs.size(); ++q) {
         const cc_batch::Seg& sg = B->segs[q];
         const cc_batch::Inst& I = B->inst[(size_t)sg.inst];
@@ -612,15 +615,16 @@ cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream)
         D = cc::SegDesc{};
         D.S = step_params(P, G, P->splits[(size_t)sg.split], I.in.colours_dev, (double*)(ws + I.arena_off),
                           pad32(G->n), (double*)(ws + I.partial_off), root_out);
-        D.item_start = item;
+        D.item_start = 0;
         D.n_items = sg.n_items;
         D.phase = sg.phase;
-        D.ndep = sg.ndep;
-        for (int d = 0; d < sg.ndep; ++d) {
-            D.dep[d] = sg.dep[d];
-            D.need[d] = (uint32_t)B->segs[(size_t)sg.dep[d]].n_items;
-        }
-        item += sg.n_items;
+    }
+    int64_t item = 0;
+    for (size_t q = 0; q < B->level_order.size(); ++q) {
+        cc::SegDesc& D = B->seg_level_host[q];
+        D = B->seg_host[(size_t)B->level_order[q]];
+        D.item_start = item;
+        item += D.n_items;
     }
     for (size_t i = 0; i < B->inst.size(); ++i) {
         const cc_batch::Inst& I = B->inst[i];
@@ -630,28 +634,35 @@ cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream)
         R.out = I.in.X_dev;
         R.partial = (double*)(ws + I.red_off);
     }
+    const bool levels = (B->flags & CC_BATCH_LEVELS) != 0;
     hipError_t e = hipSuccess;
-    if (!B->segs.empty())
-        e = hipMemcpyAsync(seg_dev, B->seg_host.data(), B->seg_host.size() * sizeof(cc::SegDesc), hipMemcpyHostToDevice, st);
+    if (!B->segs.empty()) {
+        if (levels)
+            e = hipMemcpyAsync(seg_level_dev, B->seg_level_host.data(), B->seg_level_host.size() * sizeof(cc::SegDesc),
+                               hipMemcpyHostToDevice, st);
+        else
+            e = hipMemcpyAsync(seg_dev, B->seg_host.data(), B->seg_host.size() * sizeof(cc::SegDesc),
+                               hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !levels)
+            e = hipMemcpyAsync(range_dev, B->ranges.data(), B->ranges.size() * sizeof(cc::SegRange),
+                               hipMemcpyHostToDevice, st);
+    }
     if (e == hipSuccess)
         e = hipMemcpyAsync(rd_dev, B->rd_host.data(), B->rd_host.size() * sizeof(cc::ReduceDesc), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = cc::launch_fill_u32(done, (int64_t)std::max<size_t>(B->segs.size(), 1), 0u, st);
-    if (e == hipSuccess) e = cc::launch_fill_u32(B->err_dev, 1, 0u, st);
-    // instances without splits (k = 1) or without vertices
+    // instances without splits (k = 1): every vertex roots one map
     for (size_t i = 0; e == hipSuccess && i < B->inst.size(); ++i) {
         const cc_batch::Inst& I = B->inst[i];
         if (I.in.graph->n > 0 && I.in.plan->splits.empty())
             e = cc::launch_fill_f64(const_cast<double*>(B->rd_host[i].x), I.in.graph->n, 1.0, st);
     }
-    const int64_t total = B->level_start.back();
-    if (e == hipSuccess && total > 0) {
-        if (B->flags & CC_BATCH_LEVELS) {
+    if (e == hipSuccess && !B->segs.empty()) {
+        if (levels) {
             for (size_t l = 0; e == hipSuccess && l + 1 < B->level_start.size(); ++l)
-                e = cc::launch_batch(seg_dev, (int)B->segs.size(), B->level_start[l], B->level_start[l + 1], B->J,
-                                     B->lds_wave, false, done, B->err_dev, B->n_cu, 1, st);
+                e = cc::launch_batch_level(seg_level_dev, (int)B->segs.size(), B->level_start[l], B->level_start[l + 1],
+                                           B->J, B->lds_wave, B->n_cu, st);
         } else {
-            e = cc::launch_batch(seg_dev, (int)B->segs.size(), 0, total, B->J, B->lds_wave, true, done, B->err_dev,
-                                 B->n_cu, (int)((B->flags >> 8) & 0xFFu), st);
+            e = cc::launch_batch_inst(seg_dev, range_dev, (int)B->inst.size(), B->J, B->lds_wave, B->n_cu,
+                                      (int)((B->flags >> 8) & 0xFFu), st);
         }
     }
     for (size_t i = 0; e == hipSuccess && i < B->inst.size(); ++i)
@@ -663,12 +674,9 @@ cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream)
 
 cc_status cc_batch_check(cc_batch* B, void* stream) {
     if (!B) return fail(CC_EINVAL, "NULL batch");
-    if (!B->err_dev) return CC_OK;
-    unsigned h = 0;
-    hipError_t e = hipMemcpyAsync(&h, B->err_dev, sizeof(unsigned), hipMemcpyDeviceToHost, (hipStream_t)stream);
-    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batch check");
-    if (h) return fail(CC_EINTERNAL, "a dependency wait in the persistent batch launch gave up");
     return CC_OK;
 }
 

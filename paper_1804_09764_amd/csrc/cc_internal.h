@@ -127,6 +127,12 @@ struct SegDesc {
     uint32_t need[2];    // their item counts
 };
 
+// the segments of one instance in a batch: segs[first .. first + count)
+struct SegRange {
+    int32_t first;
+    int32_t count;
+};
+
 // per-instance root reduction of a batch
 struct ReduceDesc {
     const double* x;
@@ -149,9 +155,13 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n
                            unsigned* flags, hipStream_t st);
 // mid (optional) is recorded between the gather kernel and the cut-row finish kernel
 hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid);
-// batched launch over segments [seg_lo, seg_hi) (items item_lo..item_hi); wait = honour dependencies
-hipError_t launch_batch(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J, int lds_wave,
-                        bool wait, unsigned* done, unsigned* err, int n_cu, int share, hipStream_t st);
+// batched launches: one persistent launch with instances owned by workgroups (segments of an
+// instance contiguous, in plan order; inst_dev[i] = {first segment, count}), or one launch per
+// dependency level over level-ordered segments [item_lo, item_hi)
+hipError_t launch_batch_inst(const SegDesc* segs_dev, const SegRange* inst_dev, int n_inst, int J, int lds_wave, int n_cu,
+                             int share, hipStream_t st);
+hipError_t launch_batch_level(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J,
+                              int lds_wave, int n_cu, hipStream_t st);
 hipError_t launch_reduce_batch(const ReduceDesc* rd_dev, int n_inst, int max_blocks, hipStream_t st);
 int pick_J(int Wp, int want);
 }  // namespace cc
@@ -183,12 +193,14 @@ struct cc_batch {
         int ndep;
     };
     std::vector<Inst> inst;
-    std::vector<Seg> segs;             // in launch order (by level)
+    std::vector<Seg> segs;             // instance-major, plan order within an instance
+    std::vector<cc::SegRange> ranges;  // per instance: its segments in `segs`
+    std::vector<int> level_order;      // segment ids ordered by dependency level
     std::vector<int64_t> level_start;  // item index where each level starts, plus the total
-    std::vector<cc::SegDesc> seg_host;
+    std::vector<cc::SegDesc> seg_host;        // instance-major
+    std::vector<cc::SegDesc> seg_level_host;  // level-major, item_start counted in that order
     std::vector<cc::ReduceDesc> rd_host;
-    size_t done_off = 0, err_off = 0, seg_off = 0, rd_off = 0, total = 0;
+    size_t seg_off = 0, seg_level_off = 0, range_off = 0, rd_off = 0, total = 0;
     int J = 1, lds_wave = 0, max_red_blocks = 1, n_cu = 0;
     uint32_t flags = 0;
-    unsigned* err_dev = nullptr;
 };

@@ -304,75 +304,58 @@ __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// batched launch: many (instance, split) segments in one persistent kernel
+// batched launches: many (instance, split) segments
 // ---------------------------------------------------------------------------------------------
 
-constexpr unsigned kWaitLimit = 20u * 1000u * 1000u;  // polls (each about a microsecond) before giving up
-
-// wavefront-completed items of a segment become visible to other workgroups (release)
-__device__ __forceinline__ void publish(unsigned* done, int seg, unsigned cnt, int lane) {
-    if (seg < 0 || cnt == 0) return;
-    __threadfence();
-    if (lane == 0) __hip_atomic_fetch_add(done + seg, cnt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// wait until the segments this one reads are complete (acquire); gives up after kWaitLimit polls
-__device__ __forceinline__ void wait_deps(const SegDesc& D, const unsigned* done, unsigned* err, int lane) {
-    for (int i = 0; i < D.ndep; ++i) {
-        if (lane == 0) {
-            unsigned polls = 0;
-            while (__hip_atomic_load(done + D.dep[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < D.need[i]) {
-                __builtin_amdgcn_s_sleep(16);
-                if (++polls > kWaitLimit) {
-                    atomicOr(err, 1u);
-                    break;
-                }
+// One persistent launch: each workgroup owns whole instances (round-robin over the batch) and
+// runs an instance's segments in plan order, its wavefronts sharing each segment's items; a
+// workgroup barrier separates consecutive segments. An instance's tables are written and read
+// by one workgroup only, so no device-wide synchronisation is needed.
+template <int J>
+__global__ __launch_bounds__(512) void k_batch_inst(const SegDesc* __restrict__ segs, const SegRange* __restrict__ inst,
+                                                    int n_inst, int lds_wave) {
+    extern __shared__ double lds[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    double* N = lds + (int64_t)wib * lds_wave;
+    for (int i = blockIdx.x; i < n_inst; i += gridDim.x) {
+        const SegRange range = inst[i];
+        for (int q = range.first; q < range.first + range.count; ++q) {
+            const SegDesc& D = segs[q];
+            double* Ash = N + D.S.a_off;
+            for (int64_t t = wib; t < D.n_items; t += wpb) {
+                if (D.phase == 0) do_task<J>(D.S, t, N, Ash, lane);
+                else do_hub(D.S, t, N, Ash, lane);
             }
+            __syncthreads();
         }
     }
-    __threadfence();
 }
 
-// Items [item_lo, item_hi) of the segment list are dealt round-robin to the persistent wavefronts.
-// Segments are ordered by dependency level, so every item depends only on items with smaller
-// indices; a wavefront publishes what it completed of a segment before it waits on anything, so
-// the smallest unfinished item can always run and the launch drains.
+// One launch per dependency level: items [item_lo, item_hi) of the level-ordered segment list
+// are dealt round-robin to persistent wavefronts; every item of a level is independent.
 template <int J>
-__global__ __launch_bounds__(256) void k_batch(const SegDesc* __restrict__ segs, int n_segs, int64_t item_lo,
-                                               int64_t item_hi, int lds_wave, int wpb, int wait, unsigned* done,
-                                               unsigned* err) {
+__global__ __launch_bounds__(256) void k_batch_level(const SegDesc* __restrict__ segs, int n_segs, int64_t item_lo,
+                                                     int64_t item_hi, int lds_wave, int wpb) {
     extern __shared__ double lds[];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     double* N = lds + (int64_t)wib * lds_wave;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
-    int cur = -1, verified = -1;
-    unsigned pending = 0;
+    int seg = 0;
+    int64_t seg_lo = segs[0].item_start, seg_hi = seg_lo + segs[0].n_items;
     for (int64_t t = item_lo + (int64_t)blockIdx.x * wpb + wib; t < item_hi; t += n_waves) {
-        int lo = 0, hi = n_segs;  // last segment with item_start <= t
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (segs[mid].item_start <= t) lo = mid;
-            else hi = mid;
-        }
-        const int seg = __builtin_amdgcn_readfirstlane(lo);
-        if (seg != cur) {
-            publish(done, cur, pending, lane);
-            pending = 0;
-            cur = seg;
+        while (t >= seg_hi && seg + 1 < n_segs) {  // items only increase: walk forward
+            ++seg;
+            seg_lo = segs[seg].item_start;
+            seg_hi = seg_lo + segs[seg].n_items;
         }
         const SegDesc& D = segs[seg];
-        if (wait && seg != verified) {
-            wait_deps(D, done, err, lane);
-            verified = seg;
-        }
-        const int64_t local = t - D.item_start;
         double* Ash = N + D.S.a_off;
-        if (D.phase == 0) do_task<J>(D.S, local, N, Ash, lane);
-        else do_hub(D.S, local, N, Ash, lane);
-        ++pending;
+        if (D.phase == 0) do_task<J>(D.S, t - seg_lo, N, Ash, lane);
+        else do_hub(D.S, t - seg_lo, N, Ash, lane);
     }
-    publish(done, cur, pending, lane);
 }
 
 // per-instance root sums, blocks laid out exactly as launch_reduce does for one instance
@@ -629,35 +612,64 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
     return err;
 }
 
-hipError_t launch_batch(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J, int lds_wave,
-                        bool wait, unsigned* done, unsigned* err, int n_cu, int share, hipStream_t st) {
-    if (item_hi <= item_lo) return hipSuccess;
+hipError_t launch_batch_level(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J,
+                              int lds_wave, int n_cu, hipStream_t st) {
+    if (item_hi <= item_lo || n_segs <= 0) return hipSuccess;
     if ((size_t)lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
     const int wpb = waves_for_lds(lds_wave);
     const int threads = wpb * kWave;
     const size_t lds = (size_t)lds_wave * wpb * sizeof(double);
     const void* fn = nullptr;
     switch (J) {
-        case 1: fn = (const void*)k_batch<1>; break;
-        case 2: fn = (const void*)k_batch<2>; break;
-        case 4: fn = (const void*)k_batch<4>; break;
-        default: fn = (const void*)k_batch<8>; break;
+        case 1: fn = (const void*)k_batch_level<1>; break;
+        case 2: fn = (const void*)k_batch_level<2>; break;
+        case 4: fn = (const void*)k_batch_level<4>; break;
+        default: fn = (const void*)k_batch_level<8>; break;
     }
     int per_cu = 0;
-    hipError_t err2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
-    if (err2 != hipSuccess) return err2;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    // every workgroup must be resident at once (the dependency waits rely on it)
-    int64_t blocks = (int64_t)per_cu * n_cu / (share > 1 ? share : 1);
-    if (blocks < 1) blocks = 1;
+    int64_t blocks = (int64_t)per_cu * n_cu;
     const int64_t need = (item_hi - item_lo + wpb - 1) / wpb;
     if (blocks > need) blocks = need;
-    const int w = wait ? 1 : 0;
     switch (J) {
-        case 1: hipLaunchKernelGGL(k_batch<1>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
-        case 2: hipLaunchKernelGGL(k_batch<2>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
-        case 4: hipLaunchKernelGGL(k_batch<4>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
-        default: hipLaunchKernelGGL(k_batch<8>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb, w, done, err); break;
+        case 1: hipLaunchKernelGGL(k_batch_level<1>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
+        case 2: hipLaunchKernelGGL(k_batch_level<2>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
+        case 4: hipLaunchKernelGGL(k_batch_level<4>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
+        default: hipLaunchKernelGGL(k_batch_level<8>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_inst(const SegDesc* segs_dev, const SegRange* inst_dev, int n_inst, int J, int lds_wave, int n_cu,
+                             int share, hipStream_t st) {
+    if (n_inst <= 0) return hipSuccess;
+    if ((size_t)lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
+    // up to eight wavefronts per workgroup while the LDS slices fit in 64 KB
+    int wpb = 8;
+    while (wpb > 1 && (size_t)lds_wave * wpb * sizeof(double) > 64 * 1024) wpb >>= 1;
+    const int threads = wpb * kWave;
+    const size_t lds = (size_t)lds_wave * wpb * sizeof(double);
+    const void* fn = nullptr;
+    switch (J) {
+        case 1: fn = (const void*)k_batch_inst<1>; break;
+        case 2: fn = (const void*)k_batch_inst<2>; break;
+        case 4: fn = (const void*)k_batch_inst<4>; break;
+        default: fn = (const void*)k_batch_inst<8>; break;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int64_t blocks = (int64_t)per_cu * n_cu / (share > 1 ? share : 1);
+    if (blocks < 1) blocks = 1;
+    if (blocks > n_inst) blocks = n_inst;
+    switch (J) {
+        case 1: hipLaunchKernelGGL(k_batch_inst<1>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, inst_dev, n_inst, lds_wave); break;
+        case 2: hipLaunchKernelGGL(k_batch_inst<2>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, inst_dev, n_inst, lds_wave); break;
+        case 4: hipLaunchKernelGGL(k_batch_inst<4>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, inst_dev, n_inst, lds_wave); break;
+        default: hipLaunchKernelGGL(k_batch_inst<8>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, inst_dev, n_inst, lds_wave); break;
     }
     return hipGetLastError();
 }
