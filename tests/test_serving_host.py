@@ -1,0 +1,155 @@
+"""Serving scheduler on the CPU: a simulated executor and a mocked clock.
+
+Checks admission by memory, continuous batching (new arrivals join while earlier batches run),
+first-come-first-served order, failure and cancellation handling, and latency accounting.
+"""
+import numpy as np
+import pytest
+
+from paper_1804_09764_amd.serving import Executor, Request, Server, latency_summary
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class SimExecutor(Executor):
+    """A batch takes `base + per_colouring * colourings` seconds of simulated time; X of colouring b
+    of request r is 1000 * r + b, so any mix must return exactly these values."""
+
+    def __init__(self, clock, bytes_per=None, base=0.01, per_colouring=0.001, fail_rids=()):
+        self.clock = clock
+        self.bytes_per = bytes_per or {}
+        self.base = base
+        self.per = per_colouring
+        self.fail_rids = set(fail_rids)
+        self.launched = []
+
+    def slot_bytes(self, req):
+        return self.bytes_per.get(req.rid, 100)
+
+    def launch(self, slots):
+        n = sum(s.count for s in slots)
+        h = {"end": self.clock() + self.base + self.per * n, "slots": slots, "start": self.clock()}
+        self.launched.append(h)
+        return h
+
+    def poll(self, h):
+        return self.clock() >= h["end"]
+
+    def collect(self, h):
+        if any(s.req.rid in self.fail_rids for s in h["slots"]):
+            raise RuntimeError("simulated device error")
+        return [np.array([1000.0 * s.req.rid + b for b in range(s.first, s.first + s.count)]) for s in h["slots"]]
+
+    def estimate(self, req, X):
+        return float(np.mean(X)), 0.0
+
+
+def _reqs(n, gap, B=10):
+    return [Request(rid=i, graph_id=0, tree_edges=np.array([[0, 1]]), B=B, seed=i, arrival=i * gap) for i in range(n)]
+
+
+def test_all_requests_complete_with_exact_values():
+    clk = Clock()
+    ex = SimExecutor(clk)
+    srv = Server(ex, memory_budget=10_000, max_inflight=2, max_colourings_per_batch=16, clock=clk)
+    reqs = _reqs(20, 0.003, B=13)
+    done = srv.run(reqs, sleep=clk.sleep)
+    assert len(done) == 20 and all(r.status == "done" for r in done)
+    for r in done:
+        np.testing.assert_array_equal(r.X, 1000.0 * r.rid + np.arange(r.B))
+    assert srv.stats.max_inflight_bytes <= 10_000
+    assert srv.stats.max_inflight_batches == 2
+
+
+def test_memory_budget_bounds_admission_and_queues():
+    clk = Clock()
+    ex = SimExecutor(clk, bytes_per={i: 300 for i in range(6)})
+    srv = Server(ex, memory_budget=1000, max_inflight=4, clock=clk)  # at most 3 colourings at once
+    done = srv.run(_reqs(6, 0.0, B=5), sleep=clk.sleep)
+    assert all(r.status == "done" for r in done)
+    assert srv.stats.max_inflight_bytes <= 1000
+    assert max(srv.stats.batch_sizes) <= 3
+    # with only 3 colourings in flight the 30 colourings need at least 10 batch completions
+    assert srv.stats.batches >= 10
+
+
+def test_continuous_batching_admits_arrivals_while_running():
+    clk = Clock()
+    ex = SimExecutor(clk, base=0.05, per_colouring=0.0)
+    srv = Server(ex, memory_budget=10_000, max_inflight=2, clock=clk)
+    reqs = [Request(rid=0, graph_id=0, tree_edges=np.array([[0, 1]]), B=4, seed=0, arrival=0.0),
+            Request(rid=1, graph_id=0, tree_edges=np.array([[0, 1]]), B=4, seed=1, arrival=0.01)]
+    srv.run(reqs, sleep=clk.sleep)
+    first, second = ex.launched[0], ex.launched[1]
+    assert second["start"] < first["end"]  # the second request ran while the first was on the device
+    assert reqs[1].done < reqs[0].done + 0.05
+
+
+def test_fifo_order_under_pressure():
+    clk = Clock()
+    ex = SimExecutor(clk, bytes_per={i: 400 for i in range(8)}, base=0.02)
+    srv = Server(ex, memory_budget=1000, max_inflight=1, clock=clk)
+    done = srv.run(_reqs(8, 0.0, B=3), sleep=clk.sleep)
+    order = [r.rid for r in done]
+    assert order == sorted(order)
+
+
+def test_oversized_request_fails_and_others_proceed():
+    clk = Clock()
+    ex = SimExecutor(clk, bytes_per={1: 5000})
+    srv = Server(ex, memory_budget=1000, clock=clk)
+    done = srv.run(_reqs(3, 0.001), sleep=clk.sleep)
+    by = {r.rid: r for r in done}
+    assert by[1].status == "failed" and "budget" in by[1].error
+    assert by[0].status == "done" and by[2].status == "done"
+
+
+def test_batch_failure_frees_memory_and_fails_only_its_requests():
+    clk = Clock()
+    ex = SimExecutor(clk, fail_rids={2})
+    srv = Server(ex, memory_budget=10_000, max_inflight=1, max_colourings_per_batch=10, clock=clk)
+    done = srv.run(_reqs(5, 0.05, B=10), sleep=clk.sleep)  # one request per batch
+    by = {r.rid: r for r in done}
+    assert by[2].status == "failed" and "simulated" in by[2].error
+    assert all(by[i].status == "done" for i in (0, 1, 3, 4))
+    assert srv.inflight_bytes == 0
+
+
+def test_cancel_waiting_request():
+    clk = Clock()
+    ex = SimExecutor(clk, base=1.0)
+    srv = Server(ex, memory_budget=250, max_inflight=1, clock=clk)
+    reqs = _reqs(3, 0.0, B=2)
+    for r in reqs:
+        r.arrival += clk()
+        srv.submit(r)
+    srv.step()  # admits request 0 (200 bytes), 1 and 2 wait
+    assert srv.cancel(2)
+    assert not srv.cancel(0)  # already running
+    while not srv.idle():
+        if not srv.step():
+            clk.sleep(0.01)
+    st = {r.rid: r.status for r in srv.completed}
+    assert st == {0: "done", 1: "done", 2: "cancelled"}
+
+
+def test_latency_accounting_mocked_clock():
+    clk = Clock()
+    ex = SimExecutor(clk, base=0.1, per_colouring=0.0)
+    srv = Server(ex, memory_budget=100, max_inflight=1, clock=clk)  # one colouring at a time
+    reqs = _reqs(2, 0.0, B=1)
+    srv.run(reqs, sleep=clk.sleep)
+    lat = sorted(r.latency for r in reqs)
+    assert lat[0] == pytest.approx(0.1, abs=1e-3)
+    assert lat[1] == pytest.approx(0.2, abs=1e-3)
+    s = latency_summary(reqs)
+    assert s["n"] == 2 and s["p50_s"] == pytest.approx(0.15, abs=1e-3)
