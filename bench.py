@@ -186,6 +186,10 @@ def bench(args):
     t_start = time.perf_counter()
     for i in range(args.steps):
         step(args.warmup + i)
+        if args.progress:
+            torch.cuda.synchronize()
+            print(f"[bench] step {i + 1}/{args.steps} done at {time.perf_counter() - t_start:.1f}s",
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     gather_ms, finish_ms, launches = P.profile_read()
@@ -240,6 +244,12 @@ def bench(args):
     if not args.no_batched:
         print("[bench] plain vs batched", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_plain(args)
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(args)
+        out["p50_latency_s"] = out["serving"]["p50_latency_s"]
+        out["p99_latency_s"] = out["serving"]["p99_latency_s"]
     return out
 
 
@@ -299,6 +309,94 @@ def batched_vs_plain(args, reps: int = 2):
             "levels": {"value": units / res["levels"], "ms": res["levels"] * 1e3,
                        "equal_to_plain": res["levels_equal"], "launch": "one launch per dependency level"},
             "workspace_GB": persistent.workspace_bytes / 1e9}
+
+
+SERVE_POOL = [(16 + (i % 7), (8, 16, 32)[i % 3], 100 + i) for i in range(16)]  # (scale, edge factor, seed)
+
+
+def make_requests(n, pool_size, seed, rate, k_range=(5, 12), b_range=(8, 128), t0=0.0):
+    """n requests with Poisson arrivals at `rate` per second (all at t0 if rate is 0): a graph
+    uniform over the pool, a Pruefer tree with k uniform in k_range (seeded by the request id),
+    B uniform in b_range colourings."""
+    import numpy as np
+
+    import inputs
+    from paper_1804_09764_amd.serving import Request
+    rng = np.random.default_rng(seed)
+    t = t0
+    out = []
+    for i in range(n):
+        if rate > 0:
+            t += rng.exponential(1.0 / rate)
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        B = int(rng.integers(b_range[0], b_range[1] + 1))
+        gid = int(rng.integers(0, pool_size))
+        rid = seed * 100000 + i
+        out.append(Request(rid=rid, graph_id=gid, tree_edges=inputs.pruefer_tree(k, rid), B=B, seed=rid, arrival=t))
+    return out
+
+
+def serving_leg(args):
+    """Continuous-batching server over 16 resident R-MAT graphs (scale 16..22, edge factor 8..32):
+    first the capacity with all requests queued at once, then Poisson arrivals at 80 % of it;
+    reports served CSEU/s and p50/p99 latency (arrival to result)."""
+    import torch
+
+    import inputs
+    import paper_1804_09764_amd as cc
+    from paper_1804_09764_amd.serving import GpuExecutor, Server, latency_summary
+
+    dev = torch.device("cuda:0")
+    pool = []
+    for scale, ef, seed in SERVE_POOL:
+        rp, col = inputs.rmat_graph_gpu(scale, ef, seed, device=dev)
+        pool.append(cc.Graph(rp, col, trust=True))
+    units_cache = {}
+
+    def units(r):
+        key = r.tree_edges.tobytes()
+        if key not in units_cache:
+            units_cache[key] = cc.Plan(r.tree_edges, bind=False).info.units_per_edge
+        return float(pool[r.graph_id].nnz) * units_cache[key] * r.B
+
+    ex = GpuExecutor(pool, seed_base=args.seed, n_streams=2)
+    budget = int(args.serve_budget_gb * 1e9)
+
+    def progress(r):
+        print(f"[bench] served request {r.rid}: graph {r.graph_id} k={r.k} B={r.B} {r.status} "
+              f"latency {r.latency:.2f}s", file=sys.stderr, flush=True)
+
+    # warm up (plans, allocator) on a few small requests
+    warm = make_requests(4, len(pool), seed=1, rate=0, b_range=(2, 4))
+    Server(ex, budget, max_inflight=2).run(warm)
+    torch.cuda.synchronize()
+    cap_reqs = make_requests(args.serve_capacity_requests, len(pool), seed=2, rate=0)
+    srv = Server(ex, budget, max_inflight=2, on_complete=progress)
+    t0 = time.perf_counter()
+    srv.run(cap_reqs)
+    makespan = time.perf_counter() - t0
+    capacity = len(cap_reqs) / makespan
+    cap_units = sum(units(r) for r in cap_reqs if r.status == "done")
+    rate = 0.8 * capacity
+    reqs = make_requests(args.serve_requests, len(pool), seed=9, rate=rate)
+    print(f"[bench] serving capacity {capacity:.3f} requests/s; Poisson arrivals at {rate:.3f}/s",
+          file=sys.stderr, flush=True)
+    srv2 = Server(ex, budget, max_inflight=2, on_complete=progress)
+    t0 = time.perf_counter()
+    srv2.run(reqs)
+    wall = time.perf_counter() - t0
+    lat = latency_summary(reqs)
+    served = sum(units(r) for r in reqs if r.status == "done")
+    return {"workload": "Poisson requests over 16 resident R-MAT graphs (scale 16-22, edge factor 8-32), "
+                        "Pruefer trees k in 5..12, 8..128 colourings",
+            "requests": len(reqs), "failed": sum(r.status != "done" for r in reqs),
+            "capacity_requests_per_s": capacity, "capacity_CSEU_per_s": cap_units / makespan,
+            "arrival_rate_per_s": rate, "wall_s": wall, "throughput_CSEU_per_s": served / wall,
+            "p50_latency_s": lat.get("p50_s"), "p99_latency_s": lat.get("p99_s"), "mean_latency_s": lat.get("mean_s"),
+            "batches": srv2.stats.batches,
+            "mean_colourings_per_batch": (sum(srv2.stats.batch_sizes) / max(1, srv2.stats.batches)),
+            "max_inflight_batches": srv2.stats.max_inflight_batches,
+            "memory_budget_GB": budget / 1e9, "max_inflight_GB": srv2.stats.max_inflight_bytes / 1e9}
 
 
 def summarize_pmc(args):
@@ -362,6 +460,12 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the plain-vs-batched comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--progress", type=int, default=1,
+                    help="print a line after each timed step (synchronises between steps)")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-capacity-requests", type=int, default=10)
+    ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")

@@ -358,8 +358,16 @@ class Batch:
         self.workspace_bytes = nb.value
         self._dev = instances[0][1].row_ptr.device if instances else None
 
-    def run(self, workspace: Workspace | None = None, stream=None):
-        ws = (workspace or Workspace()).get(self.workspace_bytes, self._dev)
+    def run(self, workspace=None, stream=None):
+        """Queue the batch; `workspace` is a Workspace, a uint8 GPU tensor of at least
+        workspace_bytes, or None (allocated here)."""
+        import torch
+        if isinstance(workspace, torch.Tensor):
+            if workspace.numel() < self.workspace_bytes or workspace.dtype != torch.uint8:
+                raise ValueError("workspace tensor too small")
+            ws = workspace
+        else:
+            ws = (workspace or Workspace()).get(self.workspace_bytes, self._dev)
         self._ws = ws
         _check(lib().cc_batch_run(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
 

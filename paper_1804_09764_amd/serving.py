@@ -95,8 +95,9 @@ class Stats:
 
 class Server:
     def __init__(self, executor: Executor, memory_budget: int, max_inflight: int = 2,
-                 max_colourings_per_batch: int = 256, clock=time.perf_counter):
+                 max_colourings_per_batch: int = 256, clock=time.perf_counter, on_complete=None):
         self.ex = executor
+        self.on_complete = on_complete
         self.budget = int(memory_budget)
         self.max_inflight = max_inflight
         self.max_slots = max_colourings_per_batch
@@ -156,6 +157,8 @@ class Server:
     def _finish(self, r: Request, now: float):
         r.done = now
         self.completed.append(r)
+        if self.on_complete is not None:
+            self.on_complete(r)
 
     def _complete(self, handle, slots: list[Slot], nbytes: int):
         try:
@@ -189,12 +192,14 @@ class Server:
         """Retire finished batches and launch new ones; returns True if anything happened."""
         progressed = False
         still = []
-        for handle, slots, nbytes in self.inflight:
-            if self.ex.poll(handle):
-                self._complete(handle, slots, nbytes)
+        for entry in self.inflight:
+            if self.ex.poll(entry[0]):
+                self._complete(*entry)
                 progressed = True
             else:
-                still.append((handle, slots, nbytes))
+                still.append(entry)
+        # drop every reference to finished batches (their device memory) before launching more
+        entry = None
         self.inflight = still
         while len(self.inflight) < self.max_inflight and self.queue:
             slots = self._form_batch()
@@ -280,21 +285,26 @@ class GpuExecutor(Executor):
         st = self.streams[self._rr % len(self.streams)]
         self._rr += 1
         keep, inst, outs = [], [], []
-        with torch.cuda.stream(st):
-            for s in slots:
-                g = self.graphs[s.req.graph_id]
-                p = self.plan(s.req)
-                C = cc.colour(g, p.k, seed=self.seed_base + s.req.seed, first_iter=s.first, B=s.count, stream=st)
-                X = torch.empty(s.count, dtype=torch.float64, device=self.device)
-                keep += [C, X]
-                outs.append(X)
-                for b in range(s.count):
-                    inst.append((p, g, C[b], X[b:b + 1], None))
-            batch = cc.Batch(inst, levels=True)
-            ws = cc.Workspace()
-            batch.run(ws, stream=st)
-            ev = torch.cuda.Event()
-            ev.record(st)
+        # device buffers come from the allocator's default-stream pool and are marked as used on
+        # the batch's stream, so memory freed by one batch can be reused by the next on any stream
+        for s in slots:
+            g = self.graphs[s.req.graph_id]
+            p = self.plan(s.req)
+            C = torch.empty((s.count, g.n), dtype=torch.uint8, device=self.device)
+            X = torch.empty(s.count, dtype=torch.float64, device=self.device)
+            C.record_stream(st)
+            X.record_stream(st)
+            cc.colour(g, p.k, seed=self.seed_base + s.req.seed, first_iter=s.first, B=s.count, out=C, stream=st)
+            keep += [C, X]
+            outs.append(X)
+            for b in range(s.count):
+                inst.append((p, g, C[b], X[b:b + 1], None))
+        batch = cc.Batch(inst, levels=True)
+        ws = torch.empty(max(batch.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        ws.record_stream(st)
+        batch.run(ws, stream=st)
+        ev = torch.cuda.Event()
+        ev.record(st)
         return {"event": ev, "batch": batch, "ws": ws, "keep": keep, "outs": outs, "stream": st}
 
     def poll(self, handle) -> bool:
