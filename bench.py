@@ -412,7 +412,7 @@ def summarize_pmc(args):
 
     def per_kernel(rs, counter):
         d = {}
-        for r in rs:
+        for r in sorted(rs, key=lambda r: int(r.get("Dispatch_Id", 0))):
             if r.get("Counter_Name") != counter:
                 continue
             d.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
@@ -423,9 +423,12 @@ def summarize_pmc(args):
     copy_bytes = args.copy_bytes
 
     def copy_kib(d):
-        cands = [v for name, v in d.items() if "copy" in name.lower() or "elementwise" in name.lower()]
-        vals = [max(v) for v in cands] if cands else []
-        return max(vals) if vals else None
+        # the calibration copies (bench.py --copy-calibration) are the first three device-to-device
+        # copy dispatches of the run
+        for name, v in d.items():
+            if "copybuffer" in name.lower() and len(v) >= 3:
+                return sorted(v[:3])[1]
+        return None
 
     fk, wk = copy_kib(fetch), copy_kib(write)
     f_factor = copy_bytes / (fk * 1024.0) if fk else 1.0
