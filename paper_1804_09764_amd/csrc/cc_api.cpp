@@ -113,6 +113,7 @@ cc::StepParams step_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     h.nstride = P->max_stride_N;
     h.fold = sp.fold_off >= 0 ? (const uint16_t*)(cdev + sp.fold_off) : nullptr;
     h.split = sp.split_off >= 0 ? (const uint32_t*)(cdev + sp.split_off) : nullptr;
+    h.mask = sp.mask_off >= 0 ? (const uint16_t*)(cdev + sp.mask_off) : nullptr;
     h.cols_per_lane = G->cols_per_lane;
     h.k = P->k;
     h.s = sp.s;
@@ -545,6 +546,14 @@ cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flag
                 if (sp.p >= 2)
                     B->J = std::max(B->J, cc::pick_J(sp.Wp, G->cols_per_lane));
                 B->lds_wave = std::max(B->lds_wave, cc::split_lds_wave(sp.Nw, sp.Wa, sp.a));
+                // level mode launches each split's tasks with the kernel a plain count uses
+                // (all variants sum in the same order); cut-row finishes run in variant 0
+                const int var = cc::split_variant(sp.p, sp.Wp, G->cols_per_lane);
+                const int base = cc::split_lds_wave(sp.Nw, sp.Wa, sp.a);
+                for (size_t q = (size_t)(G->n_hubs > 0 ? last[j] - 1 : last[j]); q <= (size_t)last[j]; ++q) {
+                    segs[q].variant = segs[q].phase == 0 ? var : 0;
+                    segs[q].lds_wave = base + (segs[q].phase == 0 ? cc::variant_stage(var) : 0);
+                }
             }
         }
         // instance-major order (as built) for the persistent launch; level order for the
@@ -558,19 +567,23 @@ cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flag
         }
         B->level_order.resize(segs.size());
         for (size_t q = 0; q < segs.size(); ++q) B->level_order[q] = (int)q;
-        std::stable_sort(B->level_order.begin(), B->level_order.end(),
-                         [&](int x, int y) { return segs[(size_t)x].level < segs[(size_t)y].level; });
-        int max_level = -1;
-        for (const auto& sg : segs) max_level = std::max(max_level, sg.level);
+        std::stable_sort(B->level_order.begin(), B->level_order.end(), [&](int x, int y) {
+            const cc_batch::Seg &a = segs[(size_t)x], &b = segs[(size_t)y];
+            return a.level != b.level ? a.level < b.level : a.variant < b.variant;
+        });
+        B->groups.clear();
         int64_t item = 0;
-        B->level_start.assign((size_t)(max_level + 2), 0);
-        int lvl = 0;
         for (size_t q = 0; q < B->level_order.size(); ++q) {
             const cc_batch::Seg& sg = segs[(size_t)B->level_order[q]];
-            while (lvl <= sg.level) B->level_start[(size_t)lvl++] = item;
+            if (B->groups.empty() || segs[(size_t)B->level_order[(size_t)B->groups.back().seg_lo]].level != sg.level ||
+                B->groups.back().variant != sg.variant)
+                B->groups.push_back(cc_batch::Group{(int)q, (int)q, sg.variant, 16, item, item});
+            cc_batch::Group& g = B->groups.back();
+            g.seg_hi = (int)q + 1;
+            g.item_hi = item + sg.n_items;
+            g.lds_wave = std::max(g.lds_wave, sg.lds_wave);
             item += sg.n_items;
         }
-        while (lvl <= max_level + 1) B->level_start[(size_t)lvl++] = item;
         if (B->lds_wave == 0) B->lds_wave = 16;
         const size_t nseg = std::max<size_t>(B->segs.size(), 1);
         B->seg_off = take(nseg * sizeof(cc::SegDesc));
@@ -624,6 +637,7 @@ cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream)
         cc::SegDesc& D = B->seg_level_host[q];
         D = B->seg_host[(size_t)B->level_order[q]];
         D.item_start = item;
+        D.S.stage_off = cc::split_lds_wave(D.S.Nw, D.S.Wa, D.S.a);  // narrow stage after N and A rows
         item += D.n_items;
     }
     for (size_t i = 0; i < B->inst.size(); ++i) {
@@ -657,9 +671,11 @@ cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream)
     }
     if (e == hipSuccess && !B->segs.empty()) {
         if (levels) {
-            for (size_t l = 0; e == hipSuccess && l + 1 < B->level_start.size(); ++l)
-                e = cc::launch_batch_level(seg_level_dev, (int)B->segs.size(), B->level_start[l], B->level_start[l + 1],
-                                           B->J, B->lds_wave, B->n_cu, st);
+            for (size_t l = 0; e == hipSuccess && l < B->groups.size(); ++l) {
+                const cc_batch::Group& g = B->groups[l];
+                e = cc::launch_batch_level(seg_level_dev, g.seg_lo, g.seg_hi, g.item_lo, g.item_hi, g.variant, g.lds_wave,
+                                           B->n_cu, st);
+            }
         } else {
             e = cc::launch_batch_inst(seg_dev, range_dev, (int)B->inst.size(), B->J, B->lds_wave, B->n_cu,
                                       (int)((B->flags >> 8) & 0xFFu), st);

@@ -32,6 +32,7 @@ struct Split {
     int npairs;     // C(s-1, p): splits of one output set
     int64_t split_off;  // byte offset of the pair list in the device constants (-1 if a == 1)
     int64_t fold_off;   // byte offset of the fold map in the device constants (-1 if p == 1)
+    int64_t mask_off;   // byte offset of the passive entries' colour-set masks (-1 if p == 1)
 };
 
 struct Table {
@@ -103,10 +104,12 @@ struct StepParams {
     double* partial;             // chunk partial rows
     const uint16_t* fold;
     const uint32_t* split;
+    const uint16_t* mask;        // colour set of each passive entry (over the neighbour's other colours)
     int64_t pstride, astride, ostride, nstride;
     int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
     int lds_wave;       // doubles of LDS per wavefront
     int a_off;          // offset of the staged active row inside the wavefront's LDS slice
+    int stage_off;      // offset of the narrow-row stage inside the wavefront's LDS slice
     int waves_per_block;
     int cols_per_lane;  // 0 = choose from Wp
 };
@@ -155,13 +158,17 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n
                            unsigned* flags, hipStream_t st);
 // mid (optional) is recorded between the gather kernel and the cut-row finish kernel
 hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid);
+// kernel variant of a split (general path with 1/2/4/8 doubles per lane = 0..3, or narrow rows
+// with 16/32 lanes per row = 4/5) and the LDS stage per wavefront a narrow variant adds
+int split_variant(int p, int Wp, int cols_per_lane);
+int variant_stage(int variant);
 // batched launches: one persistent launch with instances owned by workgroups (segments of an
 // instance contiguous, in plan order; inst_dev[i] = {first segment, count}), or one launch per
-// dependency level over level-ordered segments [item_lo, item_hi)
+// (dependency level, variant) group: level-ordered segments [seg_lo, seg_hi), items [item_lo, item_hi)
 hipError_t launch_batch_inst(const SegDesc* segs_dev, const SegRange* inst_dev, int n_inst, int J, int lds_wave, int n_cu,
                              int share, hipStream_t st);
-hipError_t launch_batch_level(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J,
-                              int lds_wave, int n_cu, hipStream_t st);
+hipError_t launch_batch_level(const SegDesc* segs_dev, int seg_lo, int seg_hi, int64_t item_lo, int64_t item_hi,
+                              int variant, int lds_wave, int n_cu, hipStream_t st);
 hipError_t launch_reduce_batch(const ReduceDesc* rd_dev, int n_inst, int max_blocks, hipStream_t st);
 int pick_J(int Wp, int want);
 }  // namespace cc
@@ -187,7 +194,7 @@ struct cc_batch {
         size_t arena_off, partial_off, root_off, red_off;
     };
     struct Seg {
-        int inst, split, phase, level;
+        int inst, split, phase, level, variant, lds_wave;
         int64_t n_items;
         int dep[2];
         int ndep;
@@ -195,8 +202,12 @@ struct cc_batch {
     std::vector<Inst> inst;
     std::vector<Seg> segs;             // instance-major, plan order within an instance
     std::vector<cc::SegRange> ranges;  // per instance: its segments in `segs`
-    std::vector<int> level_order;      // segment ids ordered by dependency level
-    std::vector<int64_t> level_start;  // item index where each level starts, plus the total
+    std::vector<int> level_order;      // segment ids ordered by (dependency level, kernel variant)
+    struct Group {                     // one level-mode launch
+        int seg_lo, seg_hi, variant, lds_wave;
+        int64_t item_lo, item_hi;
+    };
+    std::vector<Group> groups;
     std::vector<cc::SegDesc> seg_host;        // instance-major
     std::vector<cc::SegDesc> seg_level_host;  // level-major, item_start counted in that order
     std::vector<cc::ReduceDesc> rd_host;

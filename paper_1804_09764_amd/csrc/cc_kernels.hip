@@ -51,18 +51,21 @@ __device__ __forceinline__ void wave_sync_lds() {
 // loaded together with the row of its first member.
 template <int J, int D>
 __device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, int su, int sc, int c0, int cv,
-                                           int lane, double (&X)[D][J], int (&F)[D][J]) {
+                                           int lane, const int (&msk)[J], double (&X)[D][J], int (&F)[D][J]) {
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         const int i = b * D + q;
         if (i < cnt) {
             const int ui = bcast(su, i);
             const int ci = bcast(sc, i);
+            // position of col(v) among the colours other than col(u): entries whose set holds it
+            // are dropped by the fold, so they are not loaded (whole cache lines are skipped)
+            const int x = cv - (cv > ci ? 1 : 0);
             const double* row = S.P + (int64_t)ui * S.pstride + c0;
 #pragma unroll
             for (int t = 0; t < J; ++t) {
-                const int j = c0 + lane + kWave * t;
-                X[q][t] = (j < S.Wp) ? row[lane + kWave * t] : 0.0;
+                const bool need = (msk[t] >> x & 1) == 0;
+                X[q][t] = need ? row[lane + kWave * t] : 0.0;
             }
             const bool first = (i == 0) || (ci != bcast(sc, i > 0 ? i - 1 : 0));
             if (first) {
@@ -114,6 +117,14 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
     const int k = S.k;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
+        // colour-set masks of this lane's columns; columns past the row get an all-ones mask,
+        // which marks them as never needed
+        int msk[J];
+#pragma unroll
+        for (int t = 0; t < J; ++t) {
+            const int j = c0 + lane + kWave * t;
+            msk[t] = (j < S.Wp) ? (int)S.mask[j] : 0xFFFF;
+        }
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int64_t e = e0 + lane;
             const bool valid = e < end;
@@ -147,17 +158,99 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
                 for (int t = 0; t < J; ++t) FA[q][t] = FB[q][t] = (int)kNoSlot;
             int cur = -1;
             const int nb = (cnt + D - 1) / D;
-            load_batch<J, D>(S, 0, cnt, su, sc, c0, cv, lane, XA, FA);
+            load_batch<J, D>(S, 0, cnt, su, sc, c0, cv, lane, msk, XA, FA);
             for (int b = 0; b < nb; b += 2) {
-                if (b + 1 < nb) load_batch<J, D>(S, b + 1, cnt, su, sc, c0, cv, lane, XB, FB);
+                if (b + 1 < nb) load_batch<J, D>(S, b + 1, cnt, su, sc, c0, cv, lane, msk, XB, FB);
                 consume_batch<J, D>(b, cnt, sc, cur, N, acc, fcur, XA, FA);
                 if (b + 1 >= nb) break;
-                if (b + 2 < nb) load_batch<J, D>(S, b + 2, cnt, su, sc, c0, cv, lane, XA, FA);
+                if (b + 2 < nb) load_batch<J, D>(S, b + 2, cnt, su, sc, c0, cv, lane, msk, XA, FA);
                 consume_batch<J, D>(b + 1, cnt, sc, cur, N, acc, fcur, XB, FB);
             }
             fold_acc<J>(N, acc, fcur);
         }
     }
+}
+
+// Neighbour sum for narrow passive rows (Wp <= G <= 32): G lanes per row, so 64/G rows per load
+// instruction. The usable neighbours of a 64-entry block are sorted by colour as in gather_fold and
+// all of their rows are loaded at once and staged in LDS; each colour run is then summed column by
+// column in member order and folded into N, which is exactly gather_fold's arithmetic (same
+// order, same fold), so results do not depend on which of the two paths ran. Each lane keeps the
+// fold-map entries of its column for the colours of its slot (slot, slot + 64/G, ...).
+template <int G>
+__device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, double* stage,
+                                   int lane) {
+    constexpr int R = kWave / G;         // rows per load instruction
+    constexpr int Q = G;                 // load instructions per block of 64 members
+    constexpr int NC = (kMaxK + R - 1) / R;
+    const int k = S.k;
+    const int g = lane / G;
+    const int j = lane % G;
+    const bool colok = j < S.Wp;
+    const int mskj = colok ? (int)S.mask[j] : 0xFFFF;
+    int fidx[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+        const int c = g + m * R;
+        fidx[m] = (colok && c < k && c != cv) ? (int)S.fold[((int64_t)c * k + cv) * S.Wp + j] : (int)kNoSlot;
+    }
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t e0 = beg; e0 < end; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        const bool valid = e < end;
+        const int u = valid ? S.col[e] : 0;
+        const int cu = valid ? (int)S.colour[u] : 255;
+        const bool use = valid && cu < k && cu != cv;
+        const uint64_t used = __ballot(use);
+        const int cnt = __popcll((unsigned long long)used);
+        if (cnt == 0) continue;
+        int rank = use ? 0 : cnt + __popcll((unsigned long long)(~used & below));
+        for (int c = 0; c < k; ++c) {
+            const uint64_t bc = __ballot(use && cu == c);
+            if (use && cu > c) rank += __popcll((unsigned long long)bc);
+            if (use && cu == c) rank += __popcll((unsigned long long)(bc & below));
+        }
+        const int su = __builtin_amdgcn_ds_permute(rank << 2, u);
+        const int sc = __builtin_amdgcn_ds_permute(rank << 2, cu);
+        double x[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = q * R + g;
+            const int uq = __shfl(su, i);
+            const int cq = __shfl(sc, i);
+            const int xpos = cv - (cv > cq ? 1 : 0);
+            const bool need = i < cnt && ((mskj >> xpos) & 1) == 0;
+            x[q] = need ? S.P[(int64_t)uq * S.pstride + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) stage[(q * R + g) * G + j] = x[q];
+        wave_sync_lds();
+        int r0 = 0;
+        while (r0 < cnt) {
+            const int c = bcast(sc, r0);
+            const int r1 = r0 + __popcll((unsigned long long)__ballot(lane < cnt && sc == c));
+            int f = (int)kNoSlot;
+#pragma unroll
+            for (int m = 0; m < NC; ++m)
+                if (m == c / R) f = fidx[m];
+            const int idx = __shfl(f, (c % R) * G + j);
+            if (g == 0 && idx != (int)kNoSlot) {
+                double acc = stage[r0 * G + j];
+                for (int i = r0 + 1; i < r1; ++i) acc += stage[i * G + j];
+                N[idx] += acc;
+            }
+            r0 = r1;
+        }
+        wave_sync_lds();
+    }
+}
+
+// neighbour sum of a segment for p >= 2 (NARROW = G lanes per row, or 0 for the general path)
+template <int J, int NARROW>
+__device__ __forceinline__ void gather_rows(const StepParams& S, int64_t beg, int64_t end, int cv, double* N,
+                                            int lane) {
+    if constexpr (NARROW > 0) gather_fold_narrow<NARROW>(S, beg, end, cv, N, N + S.stage_off, lane);
+    else gather_fold<J>(S, beg, end, cv, N, lane);
 }
 
 // N[lane'] += number of neighbours in [beg, end) with colour c, lane' = c renumbered without cv
@@ -219,7 +312,7 @@ __device__ void combine_store(const StepParams& S, int v, double* N, double* Ash
 }
 
 // one light row: neighbour sum into LDS, then combine and store
-template <int J>
+template <int J, int NARROW>
 __device__ __forceinline__ void light_row(const StepParams& S, int v, double* N, double* Ash, int lane) {
     const int64_t beg = S.row_ptr[v];
     const int64_t end = S.row_ptr[v + 1];
@@ -233,14 +326,14 @@ __device__ __forceinline__ void light_row(const StepParams& S, int v, double* N,
     for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
     wave_sync_lds();
     if (S.p == 1) count_colours(S, beg, end, cv, N, lane);
-    else gather_fold<J>(S, beg, end, cv, N, lane);
+    else gather_rows<J, NARROW>(S, beg, end, cv, N, lane);
     wave_sync_lds();
     combine_store(S, v, N, Ash, lane);
     wave_sync_lds();
 }
 
 // task t of a split: a chunk of a cut row (partial N row to scratch) or a range of light rows
-template <int J>
+template <int J, int NARROW>
 __device__ __forceinline__ void do_task(const StepParams& S, int64_t t, double* N, double* Ash, int lane) {
     if (t < S.n_chunks) {
         const ChunkItem ch = S.chunks[t];
@@ -250,7 +343,7 @@ __device__ __forceinline__ void do_task(const StepParams& S, int64_t t, double* 
         wave_sync_lds();
         if (cv < S.k) {
             if (S.p == 1) count_colours(S, ch.beg, ch.beg + ch.len, cv, N, lane);
-            else gather_fold<J>(S, ch.beg, ch.beg + ch.len, cv, N, lane);
+            else gather_rows<J, NARROW>(S, ch.beg, ch.beg + ch.len, cv, N, lane);
         }
         wave_sync_lds();
         double* prow = S.partial + t * S.nstride;
@@ -259,7 +352,7 @@ __device__ __forceinline__ void do_task(const StepParams& S, int64_t t, double* 
     } else {
         const int64_t r = t - S.n_chunks;
         const int i0 = S.light_start[r], i1 = S.light_start[r + 1];
-        for (int i = i0; i < i1; ++i) light_row<J>(S, S.light[i], N, Ash, lane);
+        for (int i = i0; i < i1; ++i) light_row<J, NARROW>(S, S.light[i], N, Ash, lane);
     }
 }
 
@@ -279,7 +372,7 @@ __device__ __forceinline__ void do_hub(const StepParams& S, int64_t t, double* N
 
 // Tasks (chunks of cut rows first, then ranges of light rows, all of about `chunk` entries) are
 // dealt to the persistent wavefronts round-robin: no shared counter, one fixed owner per task.
-template <int J>
+template <int J, int NARROW>
 __global__ __launch_bounds__(256) void k_split(StepParams S) {
     extern __shared__ double lds[];
     const int lane = lane_id();
@@ -289,7 +382,7 @@ __global__ __launch_bounds__(256) void k_split(StepParams S) {
     const int64_t n_tasks = S.n_chunks + S.n_ranges;
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
     for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves)
-        do_task<J>(S, t, N, Ash, lane);
+        do_task<J, NARROW>(S, t, N, Ash, lane);
 }
 
 __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
@@ -325,7 +418,7 @@ __global__ __launch_bounds__(512) void k_batch_inst(const SegDesc* __restrict__ 
             const SegDesc& D = segs[q];
             double* Ash = N + D.S.a_off;
             for (int64_t t = wib; t < D.n_items; t += wpb) {
-                if (D.phase == 0) do_task<J>(D.S, t, N, Ash, lane);
+                if (D.phase == 0) do_task<J, 0>(D.S, t, N, Ash, lane);
                 else do_hub(D.S, t, N, Ash, lane);
             }
             __syncthreads();
@@ -333,28 +426,29 @@ __global__ __launch_bounds__(512) void k_batch_inst(const SegDesc* __restrict__ 
     }
 }
 
-// One launch per dependency level: items [item_lo, item_hi) of the level-ordered segment list
-// are dealt round-robin to persistent wavefronts; every item of a level is independent.
-template <int J>
-__global__ __launch_bounds__(256) void k_batch_level(const SegDesc* __restrict__ segs, int n_segs, int64_t item_lo,
-                                                     int64_t item_hi, int lds_wave, int wpb) {
+// One launch per (dependency level, kernel variant) group: items [item_lo, item_hi) of the
+// level-ordered segment list, which lie in segments [seg_lo, seg_hi), are dealt round-robin to
+// persistent wavefronts; every item of a level is independent.
+template <int J, int NARROW>
+__global__ __launch_bounds__(256) void k_batch_level(const SegDesc* __restrict__ segs, int seg_lo, int seg_hi,
+                                                     int64_t item_lo, int64_t item_hi, int lds_wave, int wpb) {
     extern __shared__ double lds[];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     double* N = lds + (int64_t)wib * lds_wave;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
-    int seg = 0;
-    int64_t seg_lo = segs[0].item_start, seg_hi = seg_lo + segs[0].n_items;
+    int seg = seg_lo;
+    int64_t s_begin = segs[seg].item_start, s_end = s_begin + segs[seg].n_items;
     for (int64_t t = item_lo + (int64_t)blockIdx.x * wpb + wib; t < item_hi; t += n_waves) {
-        while (t >= seg_hi && seg + 1 < n_segs) {  // items only increase: walk forward
+        while (t >= s_end && seg + 1 < seg_hi) {  // items only increase: walk forward
             ++seg;
-            seg_lo = segs[seg].item_start;
-            seg_hi = seg_lo + segs[seg].n_items;
+            s_begin = segs[seg].item_start;
+            s_end = s_begin + segs[seg].n_items;
         }
         const SegDesc& D = segs[seg];
         double* Ash = N + D.S.a_off;
-        if (D.phase == 0) do_task<J>(D.S, t - seg_lo, N, Ash, lane);
-        else do_hub(D.S, t - seg_lo, N, Ash, lane);
+        if (D.phase == 0) do_task<J, NARROW>(D.S, t - s_begin, N, Ash, lane);
+        else do_hub(D.S, t - s_begin, N, Ash, lane);
     }
 }
 
@@ -560,8 +654,12 @@ static int waves_for_lds(int lds_wave) {
 }
 
 hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) {
+    // narrow passive rows take G lanes per row (a stage of 64 rows in LDS) unless a width is forced
+    const int narrow = (S.p >= 2 && S.cols_per_lane == 0 && S.Wp <= 32) ? (S.Wp <= 16 ? 16 : 32) : 0;
     S.a_off = split_a_off(S.Nw);
     S.lds_wave = split_lds_wave(S.Nw, S.Wa, S.a);
+    S.stage_off = S.lds_wave;
+    S.lds_wave += narrow * kWave;
     if ((size_t)S.lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
     const int waves_per_block = waves_for_lds(S.lds_wave);
     const int threads = waves_per_block * kWave;
@@ -569,11 +667,13 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
     const size_t lds = (size_t)S.lds_wave * waves_per_block * sizeof(double);
     const int J = (S.p >= 2) ? pick_J(S.Wp, S.cols_per_lane) : 1;
     const void* fn = nullptr;
-    switch (J) {
-        case 1: fn = (const void*)k_split<1>; break;
-        case 2: fn = (const void*)k_split<2>; break;
-        case 4: fn = (const void*)k_split<4>; break;
-        default: fn = (const void*)k_split<8>; break;
+    if (narrow == 16) fn = (const void*)k_split<1, 16>;
+    else if (narrow == 32) fn = (const void*)k_split<1, 32>;
+    else switch (J) {
+        case 1: fn = (const void*)k_split<1, 0>; break;
+        case 2: fn = (const void*)k_split<2, 0>; break;
+        case 4: fn = (const void*)k_split<4, 0>; break;
+        default: fn = (const void*)k_split<8, 0>; break;
     }
     int per_cu = 0;
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
@@ -585,12 +685,9 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
     if (total > 0) {
-        switch (J) {
-            case 1: hipLaunchKernelGGL(k_split<1>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
-            case 2: hipLaunchKernelGGL(k_split<2>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
-            case 4: hipLaunchKernelGGL(k_split<4>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
-            default: hipLaunchKernelGGL(k_split<8>, dim3((unsigned)blocks), dim3(threads), lds, st, S); break;
-        }
+        void* args[] = {&S};
+        err = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, lds, st);
+        if (err != hipSuccess) return err;
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -612,34 +709,54 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
     return err;
 }
 
-hipError_t launch_batch_level(const SegDesc* segs_dev, int n_segs, int64_t item_lo, int64_t item_hi, int J,
-                              int lds_wave, int n_cu, hipStream_t st) {
-    if (item_hi <= item_lo || n_segs <= 0) return hipSuccess;
-    if ((size_t)lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
+// kernel variant of a split: 0..3 = general path with 1, 2, 4, 8 doubles per lane; 4, 5 = narrow
+// rows with 16 or 32 lanes per row (the choice launch_split makes for a plain count)
+int split_variant(int p, int Wp, int cols_per_lane) {
+    if (p < 2) return 0;
+    if (cols_per_lane == 0 && Wp <= 16) return 4;
+    if (cols_per_lane == 0 && Wp <= 32) return 5;
+    switch (pick_J(Wp, cols_per_lane)) {
+        case 1: return 0;
+        case 2: return 1;
+        case 4: return 2;
+        default: return 3;
+    }
+}
+
+int variant_stage(int variant) { return variant == 4 ? 16 * kWave : variant == 5 ? 32 * kWave : 0; }
+
+template <int J, int NARROW>
+static hipError_t launch_level_t(const SegDesc* segs_dev, int seg_lo, int seg_hi, int64_t item_lo, int64_t item_hi,
+                                 int lds_wave, int n_cu, hipStream_t st) {
     const int wpb = waves_for_lds(lds_wave);
     const int threads = wpb * kWave;
     const size_t lds = (size_t)lds_wave * wpb * sizeof(double);
-    const void* fn = nullptr;
-    switch (J) {
-        case 1: fn = (const void*)k_batch_level<1>; break;
-        case 2: fn = (const void*)k_batch_level<2>; break;
-        case 4: fn = (const void*)k_batch_level<4>; break;
-        default: fn = (const void*)k_batch_level<8>; break;
-    }
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_level<J, NARROW>, threads, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     int64_t blocks = (int64_t)per_cu * n_cu;
     const int64_t need = (item_hi - item_lo + wpb - 1) / wpb;
     if (blocks > need) blocks = need;
-    switch (J) {
-        case 1: hipLaunchKernelGGL(k_batch_level<1>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
-        case 2: hipLaunchKernelGGL(k_batch_level<2>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
-        case 4: hipLaunchKernelGGL(k_batch_level<4>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
-        default: hipLaunchKernelGGL(k_batch_level<8>, dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, n_segs, item_lo, item_hi, lds_wave, wpb); break;
-    }
+    hipLaunchKernelGGL((k_batch_level<J, NARROW>), dim3((unsigned)blocks), dim3(threads), lds, st, segs_dev, seg_lo,
+                       seg_hi, item_lo, item_hi, lds_wave, wpb);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_level(const SegDesc* segs_dev, int seg_lo, int seg_hi, int64_t item_lo, int64_t item_hi,
+                              int variant, int lds_wave, int n_cu, hipStream_t st) {
+    if (item_hi <= item_lo || seg_hi <= seg_lo) return hipSuccess;
+    if ((size_t)lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
+    switch (variant) {
+        case 0: return launch_level_t<1, 0>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
+        case 1: return launch_level_t<2, 0>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
+        case 2: return launch_level_t<4, 0>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
+        case 3: return launch_level_t<8, 0>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
+        case 4: return launch_level_t<1, 16>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
+        case 5: return launch_level_t<1, 32>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_batch_inst(const SegDesc* segs_dev, const SegRange* inst_dev, int n_inst, int J, int lds_wave, int n_cu,

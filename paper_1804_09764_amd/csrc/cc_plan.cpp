@@ -386,6 +386,7 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
     for (auto& sp : P->splits) {
         sp.split_off = -1;
         sp.fold_off = -1;
+        sp.mask_off = -1;
         if (sp.a >= 2) {
             // for every output set R (|R| = s-1, colex order) its p-subsets Q in increasing
             // numeric order: (rank(R \ Q), rank(Q)) packed as lo16 | hi16 << 16, layout [j][r]
@@ -429,6 +430,14 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
                 }
             const uint8_t* b = reinterpret_cast<const uint8_t*>(tab.data());
             C.insert(C.end(), b, b + tab.size() * 2);
+            // set of passive entry j as a bit mask over the k-1 colours other than the
+            // neighbour's: entry j is of no use to v when it contains col(v)'s position there
+            align();
+            sp.mask_off = (int64_t)C.size();
+            std::vector<uint16_t> mk(rows.size());
+            for (size_t j = 0; j < rows.size(); ++j) mk[j] = (uint16_t)rows[j];
+            const uint8_t* bm = reinterpret_cast<const uint8_t*>(mk.data());
+            C.insert(C.end(), bm, bm + mk.size() * 2);
         }
     }
     align();
