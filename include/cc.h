@@ -186,6 +186,30 @@ cc_status cc_count(const cc_plan* plan, const cc_graph* g, const uint8_t* colour
                    void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Packed count: B colourings of one template in one pass over the graph                        */
+/* ------------------------------------------------------------------------------------------ */
+
+#define CC_MAX_PACKED 4096  /* largest B of a packed count */
+
+/* Device workspace needed by cc_count_packed for this plan, graph and B. */
+cc_status cc_count_packed_workspace_bytes(const cc_plan* plan, const cc_graph* g, int32_t B, size_t* bytes);
+
+/*
+ * The outer loop of Algorithm 1 (Section 2.1) over B colourings, evaluated together: every table
+ * row holds the counts of all B colourings side by side (row v = [colouring][colour set]), so each
+ * split reads a neighbour's row and CSR entry once for all colourings. Computes, for b in [0, B),
+ * the same X_dev[b] as cc_count (Eq. 1 applied per colouring): exact below 2^53, and above it
+ * within the rounding of a different but fixed summation order (every neighbour sum adds its
+ * terms in CSR order), so a colouring's result does not depend on B or on the other colourings.
+ * colours_dev: B*n bytes, colouring b at colours_dev + b*n (the layout cc_color writes).
+ * vertex_dev (optional, may be NULL): n*B doubles, vertex_dev[v*B + b] = the maps of colouring b
+ * with phi(root) = v. CC_ERANGE when B is outside [1, CC_MAX_PACKED] or when a split of the plan
+ * is too wide for the packed kernels (templates of up to 12 vertices always fit).
+ */
+cc_status cc_count_packed(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
+                          void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Batched count: many colourings and templates, on one or more graphs, in one launch          */
 /* (the independent outer iterations of Algorithm 1 run together)                              */
 /* ------------------------------------------------------------------------------------------ */

@@ -72,6 +72,7 @@ class _Tuning(ctypes.Structure):
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
            "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
+           "cc_count_packed_workspace_bytes", "cc_count_packed",
            "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read",
            "cc_batch_create", "cc_batch_workspace_bytes", "cc_batch_run", "cc_batch_check", "cc_batch_destroy"]
 
@@ -100,6 +101,8 @@ def lib() -> ctypes.CDLL:
         "cc_color": (ctypes.c_int, [P, I32, U64, U64, I32, P, P]),
         "cc_count_workspace_bytes": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
+        "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
+        "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_estimate": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
         "cc_estimate_median_of_means": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ctypes.c_double)]),
@@ -310,6 +313,35 @@ def count(plan: Plan, graph: Graph, colours, per_vertex: bool = False, workspace
     _check(lib().cc_count(plan.handle, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B,
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dev_ptr(X, torch.float64, "X"),
                           _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
+    return (X, V) if per_vertex else X
+
+
+def count_packed_workspace_bytes(plan: Plan, graph: Graph, B: int) -> int:
+    nb = ctypes.c_size_t()
+    _check(lib().cc_count_packed_workspace_bytes(plan.handle, graph.handle, B, ctypes.byref(nb)))
+    return nb.value
+
+
+def count_packed(plan: Plan, graph: Graph, colours, per_vertex: bool = False, workspace: Workspace | None = None,
+                 out=None, vertex_out=None, stream=None):
+    """X[b] for the B colourings of `colours` ([B, n] uint8 on the GPU) counted together, one row of
+    the tables holding all B colourings (cc_count_packed). The per-vertex counts, if asked, are
+    [n, B]."""
+    import torch
+    if colours.dim() == 1:
+        colours = colours.view(1, -1)
+    B = colours.shape[0]
+    if colours.shape[1] != graph.n:
+        raise ValueError("colours must be [B, n]")
+    dev = graph.row_ptr.device
+    ws = (workspace or Workspace()).get(count_packed_workspace_bytes(plan, graph, B), dev)
+    X = out if out is not None else torch.empty(B, dtype=torch.float64, device=dev)
+    V = None
+    if per_vertex:
+        V = vertex_out if vertex_out is not None else torch.empty((graph.n, B), dtype=torch.float64, device=dev)
+    _check(lib().cc_count_packed(plan.handle, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dev_ptr(X, torch.float64, "X"),
+                                 _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
     return (X, V) if per_vertex else X
 
 

@@ -17,8 +17,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 
 
 def sources() -> list[str]:
-    return [os.path.join(CSRC, s) for s in SOURCES] + [os.path.join(CSRC, "cc_internal.h"),
-                                                        os.path.join(os.path.dirname(PKG), "include", "cc.h")]
+    headers = [os.path.join(CSRC, h) for h in ("cc_internal.h", "cc_device.h", "cc_packed.h")]
+    return [os.path.join(CSRC, s) for s in SOURCES] + headers + [os.path.join(os.path.dirname(PKG), "include", "cc.h")]
 
 
 def build(verbose: bool = False) -> str:

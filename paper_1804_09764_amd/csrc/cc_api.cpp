@@ -75,6 +75,29 @@ CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
     return L;
 }
 
+// workspace of a packed count with B colourings per row
+struct PackedLayout {
+    size_t arena_off, partial_off, root_off, colour_off, red_off, total;
+    int64_t n_pad, nstride;
+    std::vector<int64_t> col_off, stride;
+};
+
+PackedLayout packed_layout(const cc_plan* P, const cc_graph* G, int32_t B) {
+    PackedLayout L;
+    L.n_pad = pad32(G->n);
+    const int64_t cols = cc::packed_arena(P, B, &L.col_off, &L.stride);
+    int64_t nst = 1;
+    for (const auto& sp : P->splits) nst = std::max(nst, cc::packed_stride((int64_t)B * sp.Cf));
+    L.nstride = nst;
+    L.arena_off = 0;
+    L.partial_off = align256((size_t)cols * (size_t)L.n_pad * sizeof(double));
+    L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)nst * sizeof(double));
+    L.colour_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * (size_t)B * sizeof(double));
+    L.red_off = align256(L.colour_off + (size_t)std::max<int64_t>(G->n, 1) * (size_t)B);
+    L.total = align256(L.red_off + (size_t)cc::packed_reduce_blocks(G->n) * (size_t)B * sizeof(double));
+    return L;
+}
+
 // arguments of split `sp` of plan P on graph G for one colouring; tables live in `arena`
 cc::StepParams step_params(const cc_plan* P, const cc_graph* G, const cc::Split& sp, const uint8_t* colour,
                            double* arena, int64_t n_pad, double* partial, double* root_out) {
@@ -127,6 +150,53 @@ cc::StepParams step_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     h.a_off = cc::split_a_off(sp.Nw);
     h.lds_wave = cc::split_lds_wave(sp.Nw, sp.Wa, sp.a);
     return h;
+}
+
+// the same split over the packed layout (B colourings per row, colours as [v][b])
+cc::StepParams packed_step_params(const cc_plan* P, const cc_graph* G, const cc::Split& sp, const uint8_t* colour,
+                                  double* arena, const PackedLayout& L, double* partial, double* root_out, int32_t B) {
+    cc::StepParams h = step_params(P, G, sp, colour, arena, L.n_pad, partial, root_out);
+    if (sp.pas >= 0) {
+        h.P = arena + L.col_off[(size_t)sp.pas] * L.n_pad;
+        h.pstride = L.stride[(size_t)sp.pas];
+    }
+    if (sp.act >= 0) {
+        h.A = arena + L.col_off[(size_t)sp.act] * L.n_pad;
+        h.astride = L.stride[(size_t)sp.act];
+    }
+    if (sp.out >= 0) {
+        h.O = arena + L.col_off[(size_t)sp.out] * L.n_pad;
+        h.ostride = L.stride[(size_t)sp.out];
+    } else {
+        h.O = root_out;
+        h.ostride = B;
+    }
+    h.nstride = L.nstride;
+    const uint8_t* cdev = (const uint8_t*)P->dev;
+    h.B = B;
+    h.Cf = sp.Cf;
+    h.fullmap = sp.full_off >= 0 ? (const uint16_t*)(cdev + sp.full_off) : nullptr;
+    h.emap = (const uint16_t*)(cdev + sp.emap_off);
+    cc::packed_tile(&h);
+    return h;
+}
+
+// every split of the plan fits the packed kernels' LDS (one wavefront's slice and the maps)
+bool packed_fits(const cc_plan* P, int32_t B) {
+    for (const auto& sp : P->splits) {
+        cc::StepParams h{};
+        h.k = P->k;
+        h.a = sp.a;
+        h.p = sp.p;
+        h.Wa = sp.Wa;
+        h.Wp = sp.Wp;
+        h.Nw = sp.Nw;
+        h.Cf = sp.Cf;
+        h.B = B;
+        cc::packed_tile(&h);
+        if (cc::packed_lds_bytes(h, 1) > 64 * 1024) return false;
+    }
+    return true;
 }
 
 }  // namespace
@@ -468,6 +538,61 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
         if (e == hipSuccess) e = cc::launch_reduce(root_out, n, red, X_dev + b, st);
         if (e != hipSuccess) return hip_fail(e, "count launch");
     }
+    return CC_OK;
+}
+
+cc_status cc_count_packed_workspace_bytes(const cc_plan* P, const cc_graph* G, int32_t B, size_t* bytes) {
+    if (!P || !G || !bytes) return fail(CC_EINVAL, "NULL argument");
+    if (B < 1 || B > CC_MAX_PACKED) return fail(CC_ERANGE, "B must be in [1, CC_MAX_PACKED]");
+    *bytes = packed_layout(P, G, B).total;
+    return CC_OK;
+}
+
+cc_status cc_count_packed(const cc_plan* P, const cc_graph* G, const uint8_t* colours_dev, int32_t B, void* ws_dev,
+                          size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream) {
+    if (!P || !G) return fail(CC_EINVAL, "NULL plan or graph");
+    if (B < 1 || B > CC_MAX_PACKED) return fail(CC_ERANGE, "B must be in [1, CC_MAX_PACKED]");
+    if (!X_dev || !ws_dev || (G->n > 0 && !colours_dev)) return fail(CC_EINVAL, "NULL buffer");
+    if (!P->splits.empty() && !P->dev) return fail(CC_EINVAL, "plan not bound to device memory");
+    if (!packed_fits(P, B)) return fail(CC_ERANGE, "template too large for the packed layout (use cc_count)");
+    PackedLayout L = packed_layout(P, G, B);
+    if (ws_bytes < L.total) return fail(CC_ENOSPC, "count workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)ws_dev;
+    const int64_t n = G->n;
+    hipError_t e = hipSuccess;
+    if (n == 0) {
+        e = cc::launch_fill_f64(X_dev, B, 0.0, st);
+        if (e != hipSuccess) return hip_fail(e, "fill");
+        return CC_OK;
+    }
+    double* arena = (double*)(ws + L.arena_off);
+    double* partial = (double*)(ws + L.partial_off);
+    double* root_out = vertex_dev ? vertex_dev : (double*)(ws + L.root_off);
+    uint8_t* cpk = ws + L.colour_off;
+    double* red = (double*)(ws + L.red_off);
+    e = cc::launch_transpose_colours(colours_dev, n, B, cpk, st);
+    if (e == hipSuccess && P->splits.empty()) e = cc::launch_fill_f64(root_out, n * B, 1.0, st);
+    for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
+        const cc::Split& sp = P->splits[i];
+        cc::StepParams h = packed_step_params(P, G, sp, cpk, arena, L, partial, root_out, B);
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        if (P->profiling) {
+            for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+            if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+        }
+        if (e == hipSuccess) e = cc::launch_packed_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
+        if (e == hipSuccess && P->profiling) {
+            e = hipEventRecord(ev[2], st);
+            auto& pe = P->prof_events[i];
+            pe.push_back(ev[0]);
+            pe.push_back(ev[1]);
+            pe.push_back(ev[2]);
+            P->prof_launches[i] += 1;
+        }
+    }
+    if (e == hipSuccess) e = cc::launch_reduce_packed(root_out, n, B, red, X_dev, st);
+    if (e != hipSuccess) return hip_fail(e, "packed count launch");
     return CC_OK;
 }
 

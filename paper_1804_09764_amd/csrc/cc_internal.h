@@ -33,6 +33,11 @@ struct Split {
     int64_t split_off;  // byte offset of the pair list in the device constants (-1 if a == 1)
     int64_t fold_off;   // byte offset of the fold map in the device constants (-1 if p == 1)
     int64_t mask_off;   // byte offset of the passive entries' colour-set masks (-1 if p == 1)
+    // packed layout (several colourings per row): neighbour sums are kept over all k colours,
+    // C(k, p) entries per colouring
+    int Cf;             // C(k, p)
+    int64_t full_off;   // byte offset of FM[cu][j]: full-space rank of passive entry j (-1 if p == 1)
+    int64_t emap_off;   // byte offset of E[cv][q]: full-space rank of N entry q written without cv
 };
 
 struct Table {
@@ -88,6 +93,12 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
 
 int pad_stride(int W);
 
+// Table arena of a packed count with B colourings per row: the plan's allocation sequence replayed
+// with rows of B * W doubles (row stride rounded up to 16 doubles). Returns the arena width in
+// columns; col_off[t] and stride[t] per table.
+int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off, std::vector<int64_t>* stride);
+inline int64_t packed_stride(int64_t W) { return (W + 15) / 16 * 16; }
+
 // Arguments of one split over one graph and one colouring (shared by host and device code).
 struct StepParams {
     const int64_t* row_ptr;
@@ -112,6 +123,15 @@ struct StepParams {
     int stage_off;      // offset of the narrow-row stage inside the wavefront's LDS slice
     int waves_per_block;
     int cols_per_lane;  // 0 = choose from Wp
+    // packed layout: B colourings per row, row v = [b][entry] (entry block of colouring b at
+    // b * W); colour points to the colours as [v][b]. B == 0 selects the one-colouring layout.
+    int B;
+    int bt;             // colourings per tile of a row (<= 64)
+    int Cf;             // C(k, p): neighbour-sum entries per colouring, over all k colours
+    int tab_u16;        // entries of the block-shared maps at the start of LDS: FM (k * Wp) then E (k * Nw)
+    int tab_doubles;    // their size in doubles (rounded up)
+    const uint16_t* fullmap;  // FM[cu][j] (p >= 2)
+    const uint16_t* emap;     // E[cv][q]
 };
 
 // LDS layout of one split: N row (padded), then the active row when a >= 2
@@ -171,6 +191,14 @@ hipError_t launch_batch_level(const SegDesc* segs_dev, int seg_lo, int seg_hi, i
                               int variant, int lds_wave, int n_cu, hipStream_t st);
 hipError_t launch_reduce_batch(const ReduceDesc* rd_dev, int n_inst, int max_blocks, hipStream_t st);
 int pick_J(int Wp, int want);
+// packed layout: tile choice and LDS size of one split (host), the split launch, the [B][n] ->
+// [n][B] colour transpose and the per-colouring root sums of a [n][B] table
+void packed_tile(StepParams* S);
+size_t packed_lds_bytes(const StepParams& S, int waves);
+hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid);
+hipError_t launch_transpose_colours(const uint8_t* in, int64_t n, int B, uint8_t* out, hipStream_t st);
+int packed_reduce_blocks(int64_t n);
+hipError_t launch_reduce_packed(const double* x, int64_t n, int B, double* partial, double* out, hipStream_t st);
 }  // namespace cc
 
 struct cc_graph {

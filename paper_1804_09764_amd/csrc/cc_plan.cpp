@@ -298,6 +298,24 @@ Schedule schedule(int k, const Rooted& R, int root) {
 
 }  // namespace
 
+int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off, std::vector<int64_t>* stride) {
+    // the allocation order of schedule(): each split allocates its output table, then releases
+    // its active and passive inputs
+    Arena A;
+    col_off->assign(P->tables.size(), 0);
+    stride->assign(P->tables.size(), 0);
+    for (const Split& sp : P->splits) {
+        if (sp.out >= 0) {
+            const int64_t w = packed_stride((int64_t)B * P->tables[(size_t)sp.out].W);
+            (*stride)[(size_t)sp.out] = w;
+            (*col_off)[(size_t)sp.out] = A.alloc(w);
+        }
+        if (sp.act >= 0) A.release((*col_off)[(size_t)sp.act]);
+        if (sp.pas >= 0) A.release((*col_off)[(size_t)sp.pas]);
+    }
+    return A.peak;
+}
+
 cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_plan* P,
                      std::string* err) {
     if (k < 1 || k > kMaxK) {
@@ -387,6 +405,9 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
         sp.split_off = -1;
         sp.fold_off = -1;
         sp.mask_off = -1;
+        sp.full_off = -1;
+        sp.emap_off = -1;
+        sp.Cf = (int)binom(k, sp.p);
         if (sp.a >= 2) {
             // for every output set R (|R| = s-1, colex order) its p-subsets Q in increasing
             // numeric order: (rank(R \ Q), rank(Q)) packed as lo16 | hi16 << 16, layout [j][r]
@@ -438,6 +459,28 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
             for (size_t j = 0; j < rows.size(); ++j) mk[j] = (uint16_t)rows[j];
             const uint8_t* bm = reinterpret_cast<const uint8_t*>(mk.data());
             C.insert(C.end(), bm, bm + mk.size() * 2);
+            // packed layout: FM[cu][j] = colex rank over all k colours of R_u + {cu}
+            align();
+            sp.full_off = (int64_t)C.size();
+            std::vector<uint16_t> fm((size_t)k * rows.size(), kNoSlot);
+            for (int cu = 0; cu < k; ++cu)
+                for (size_t j = 0; j < rows.size(); ++j)
+                    fm[(size_t)cu * rows.size() + j] = (uint16_t)colex_rank(expand_bits(rows[j], cu) | (1u << cu));
+            const uint8_t* bf = reinterpret_cast<const uint8_t*>(fm.data());
+            C.insert(C.end(), bf, bf + fm.size() * 2);
+        }
+        // packed layout: E[cv][q] = colex rank over all k colours of the p-set whose rank over the
+        // colours other than cv is q
+        {
+            align();
+            sp.emap_off = (int64_t)C.size();
+            auto qs = masks_of(K, sp.p);
+            std::vector<uint16_t> em((size_t)k * qs.size());
+            for (int cv = 0; cv < k; ++cv)
+                for (size_t q = 0; q < qs.size(); ++q)
+                    em[(size_t)cv * qs.size() + q] = (uint16_t)colex_rank(expand_bits(qs[q], cv));
+            const uint8_t* be = reinterpret_cast<const uint8_t*>(em.data());
+            C.insert(C.end(), be, be + em.size() * 2);
         }
     }
     align();

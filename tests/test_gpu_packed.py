@@ -1,0 +1,198 @@
+"""GPU parity of the packed count (B colourings per table row) against the oracle.
+
+Every colouring of a packed count is checked against the oracle's count for that colouring alone:
+bit-identical below 2^53, within 1e-12 relative above. Per-vertex counts come back as [n][B].
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TWO53 = float(2 ** 53)
+
+
+def _cc():
+    import paper_1804_09764_amd as cc
+    return cc
+
+
+def assert_parity(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape
+    small = ref < TWO53
+    np.testing.assert_array_equal(gpu[small], ref[small])
+    if (~small).any():
+        rel = np.abs(gpu[~small] - ref[~small]) / ref[~small]
+        assert rel.max() <= 1e-12, rel.max()
+
+
+def packed(rp, cl, cols, T, root=-1, hub_threshold=0, chunk=0):
+    """cols: [B, n] uint8 (numpy). Returns X [B], V [n, B] (numpy), the plan and the graph."""
+    import torch
+    cc = _cc()
+    G = cc.Graph.from_numpy(rp, cl, hub_threshold=hub_threshold, chunk=chunk)
+    P = cc.Plan(T, root=root)
+    C = torch.from_numpy(np.ascontiguousarray(cols, dtype=np.uint8)).cuda()
+    X, V = cc.count_packed(P, G, C, per_vertex=True)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), V.cpu().numpy(), P, G
+
+
+def check_packed(rp, cl, cols, T, root=-1, which=None, **kw):
+    X, V, P, G = packed(rp, cl, cols, T, root=root, **kw)
+    for b in (range(len(cols)) if which is None else which):
+        Xo, Vo = oracle.count(rp, cl, cols[b], T, root=P.info.root, per_vertex=True)
+        assert_parity(V[:, b], Vo)
+        assert_parity([X[b]], [Xo])
+    return X, P, G
+
+
+def oracle_colourings(n, k, B, seed):
+    return np.stack([oracle.colour(seed, b, n, k) for b in range(B)])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_packed_tiny_all_trees_all_roots(dev, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(10, 16))
+    rp, cl = inputs.er_graph(n, 3 * n, seed)
+    for k in range(1, 8):
+        cols = oracle_colourings(n, k, 5, 100 * seed + k)
+        for ti, T in enumerate(inputs.all_trees(k)):
+            for root in range(k):
+                print(f"case: packed tiny n={n} k={k} tree={ti} root={root} B=5", flush=True)
+                check_packed(rp, cl, cols, T, root=root)
+
+
+@pytest.mark.parametrize("B", [1, 2, 63, 64, 65, 130])
+def test_packed_tiles_and_hub_chunks(dev, B):
+    """B below, at and above one tile of 64 colourings; rows cut into chunks."""
+    rp, cl = inputs.rmat_graph(10, 16, 4)
+    n = len(rp) - 1
+    for k, T in ((4, inputs.star_tree(4)), (7, inputs.pruefer_tree(7, 5))):
+        cols = oracle_colourings(n, k, B, 7 + k)
+        which = sorted({0, B // 2, B - 1})
+        print(f"case: packed rmat10 k={k} B={B} hubs", flush=True)
+        X1, _, G1 = check_packed(rp, cl, cols, T, which=which, hub_threshold=64, chunk=64)
+        assert G1.info["n_hubs"] > 0
+        X2, _, G2 = check_packed(rp, cl, cols, T, which=which[:1], hub_threshold=1 << 20, chunk=64)
+        assert G2.info["n_hubs"] == 0
+        assert_parity(X1, X2)
+
+
+def test_packed_result_independent_of_B(dev):
+    """A colouring's count is bit-identical whatever else is packed with it."""
+    import torch
+    cc = _cc()
+    rp, cl = inputs.rmat_graph(11, 16, 6)
+    G = cc.Graph.from_numpy(rp, cl, hub_threshold=128, chunk=64)
+    for k in (7, 9):
+        T = inputs.pruefer_tree(k, 21 + k)
+        P = cc.Plan(T)
+        C = cc.colour(G, k, seed=99, first_iter=0, B=70)
+        full = cc.count_packed(P, G, C)
+        part = cc.count_packed(P, G, C[3:8].contiguous())
+        one = cc.count_packed(P, G, C[5:6].contiguous())
+        plain = cc.count(P, G, C[:4].contiguous())
+        torch.cuda.synchronize()
+        print(f"case: packed B-independence k={k}", flush=True)
+        assert torch.equal(full[3:8], part)
+        assert torch.equal(full[5:6], one)
+        assert_parity(full[:4].cpu().numpy(), plain.cpu().numpy())
+        Xo = [oracle.count(rp, cl, C[b].cpu().numpy(), T) for b in (0, 69)]
+        assert_parity(full[[0, 69]].cpu().numpy(), Xo)
+
+
+@pytest.mark.parametrize("k", [10, 12])
+def test_packed_wide_tables(dev, k):
+    rp, cl = inputs.rmat_graph(8, 8, 2)
+    n = len(rp) - 1
+    cols = oracle_colourings(n, k, 3, k)
+    for seed in (12, 13):
+        print(f"case: packed rmat8 wide k={k} seed={seed}", flush=True)
+        check_packed(rp, cl, cols, inputs.pruefer_tree(k, seed), hub_threshold=128, chunk=64)
+    check_packed(rp, cl, cols, inputs.path_tree(k))
+
+
+@pytest.mark.parametrize("k", [13, 14, 16])
+def test_packed_large_k_counts_or_refuses(dev, k):
+    """Wider templates either count exactly or are refused with CC_ERANGE before any launch."""
+    cc = _cc()
+    rp, cl = inputs.er_graph(60, 240, k)
+    cols = oracle_colourings(60, k, 2, k)
+    for T in (inputs.path_tree(k), inputs.pruefer_tree(k, 3)):
+        print(f"case: packed er60 k={k}", flush=True)
+        try:
+            check_packed(rp, cl, cols, T)
+        except cc.CCError as e:
+            assert e.status == -2, e
+
+
+def test_packed_above_2_53(dev):
+    rp, cl = inputs.clique_graph(80)
+    cols = oracle_colourings(80, 12, 2, 5)
+    X, _, _ = check_packed(rp, cl, cols, inputs.path_tree(12))
+    assert X.min() > TWO53
+    rp, cl = inputs.rmat_graph(10, 32, 7)
+    n = len(rp) - 1
+    cols = oracle_colourings(n, 9, 4, 5)
+    check_packed(rp, cl, cols, inputs.pruefer_tree(9, 1), hub_threshold=64, chunk=64)
+
+
+def _without(rp, cl, keep):
+    """Induced subgraph on the vertices with keep[v], relabelled in order."""
+    n = len(rp) - 1
+    new = -np.ones(n, dtype=np.int64)
+    new[keep] = np.arange(int(keep.sum()))
+    src = np.repeat(np.arange(n), np.diff(rp))
+    m = keep[src] & keep[cl]
+    return inputs.csr_from_edges(int(keep.sum()), list(zip(new[src[m]].tolist(), new[cl[m]].tolist())))
+
+
+def test_invalid_colours_exclude_vertices(dev):
+    """A vertex whose colour is outside [0, k) takes part in no map: both count paths equal the
+    oracle on the graph without those vertices."""
+    import torch
+    cc = _cc()
+    rp, cl = inputs.rmat_graph(9, 8, 3)
+    n = len(rp) - 1
+    k = 6
+    T = inputs.pruefer_tree(k, 2)
+    cols = oracle_colourings(n, k, 3, 17)
+    rng = np.random.default_rng(4)
+    for b in range(3):
+        cols[b, rng.choice(n, n // (4 + b), replace=False)] = [k, 200, 255][b]
+    Xp, Vp, P, _ = packed(rp, cl, cols, T, hub_threshold=64, chunk=64)
+    G = cc.Graph.from_numpy(rp, cl, hub_threshold=64, chunk=64)
+    Xs, Vs = cc.count(P, G, torch.from_numpy(cols).cuda(), per_vertex=True)
+    torch.cuda.synchronize()
+    for b in range(3):
+        keep = cols[b] < k
+        rp2, cl2 = _without(rp, cl, keep)
+        Xo, Vo = oracle.count(rp2, cl2, cols[b][keep], T, root=P.info.root, per_vertex=True)
+        full = np.zeros(n)
+        full[keep] = Vo
+        print(f"case: invalid colours b={b}", flush=True)
+        assert_parity(Vp[:, b], full)
+        assert_parity(Vs.cpu().numpy()[b], full)
+        assert_parity([Xp[b], Xs.cpu().numpy()[b]], [Xo, Xo])
+
+
+def test_packed_empty_and_degenerate(dev):
+    import torch
+    cc = _cc()
+    rp = np.zeros(11, dtype=np.int64)
+    cl = np.zeros(0, dtype=np.int32)
+    G = cc.Graph.from_numpy(rp, cl)
+    for k in (1, 2, 5):
+        P = cc.Plan(inputs.path_tree(k))
+        C = cc.colour(G, k, 1, 0, 3)
+        X = cc.count_packed(P, G, C)
+        torch.cuda.synchronize()
+        assert X.cpu().tolist() == ([10.0] * 3 if k == 1 else [0.0] * 3)
+    with pytest.raises(cc.CCError):
+        cc.count_packed(cc.Plan(inputs.path_tree(3)), G, torch.zeros((0, 10), dtype=torch.uint8, device="cuda"))
