@@ -79,13 +79,22 @@ CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
 struct PackedLayout {
     size_t arena_off, partial_off, root_off, colour_off, red_off, total;
     int64_t n_pad, nstride;
-    std::vector<int64_t> col_off, stride;
+    std::vector<int64_t> col_off;  // per table, in columns of n_pad doubles
+    std::vector<int64_t> stride;   // per table: doubles between consecutive vertices
+    std::vector<int64_t> bstep;    // per table: doubles between consecutive colourings
 };
 
 PackedLayout packed_layout(const cc_plan* P, const cc_graph* G, int32_t B) {
     PackedLayout L;
     L.n_pad = pad32(G->n);
-    const int64_t cols = cc::packed_arena(P, B, &L.col_off, &L.stride);
+    const int64_t cols = cc::packed_arena(P, B, &L.col_off);
+    L.stride.resize(P->tables.size());
+    L.bstep.resize(P->tables.size());
+    for (size_t t = 0; t < P->tables.size(); ++t) {
+        const int64_t W = P->tables[t].W;
+        L.stride[t] = cc::packed_wide(W) ? cc::packed_stride(W) : cc::packed_stride((int64_t)B * W);
+        L.bstep[t] = cc::packed_wide(W) ? L.n_pad * cc::packed_stride(W) : W;
+    }
     int64_t nst = 1;
     for (const auto& sp : P->splits) nst = std::max(nst, cc::packed_stride((int64_t)B * sp.Cf));
     L.nstride = nst;
@@ -105,6 +114,7 @@ cc::StepParams step_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     h.row_ptr = G->row_ptr;
     h.col = G->col;
     h.colour = colour;
+    h.cstride = 1;
     h.light = G->light;
     h.light_start = G->light_start;
     h.chunks = G->chunks;
@@ -181,9 +191,36 @@ cc::StepParams packed_step_params(const cc_plan* P, const cc_graph* G, const cc:
     return h;
 }
 
-// every split of the plan fits the packed kernels' LDS (one wavefront's slice and the maps)
+// split `sp` of a packed count for colouring b alone, with the one-colouring kernels: the tables
+// are the packed ones offset to colouring b's entry blocks; colours_bn is the caller's [B][n]
+// colour array (colouring b's colours are contiguous there, a small, cache-resident array)
+cc::StepParams packed_one_params(const cc_plan* P, const cc_graph* G, const cc::Split& sp, const uint8_t* colours_bn,
+                                 double* arena, const PackedLayout& L, double* partial, double* root_out, int32_t B,
+                                 int32_t b) {
+    cc::StepParams h = step_params(P, G, sp, colours_bn + (int64_t)b * G->n, arena, L.n_pad, partial, root_out);
+    if (sp.pas >= 0) {
+        h.P = arena + L.col_off[(size_t)sp.pas] * L.n_pad + (int64_t)b * L.bstep[(size_t)sp.pas];
+        h.pstride = L.stride[(size_t)sp.pas];
+    }
+    if (sp.act >= 0) {
+        h.A = arena + L.col_off[(size_t)sp.act] * L.n_pad + (int64_t)b * L.bstep[(size_t)sp.act];
+        h.astride = L.stride[(size_t)sp.act];
+    }
+    if (sp.out >= 0) {
+        h.O = arena + L.col_off[(size_t)sp.out] * L.n_pad + (int64_t)b * L.bstep[(size_t)sp.out];
+        h.ostride = L.stride[(size_t)sp.out];
+    } else {
+        h.O = root_out + b;
+        h.ostride = B;
+    }
+    return h;
+}
+
+// every split of the plan that runs the packed kernels fits their LDS (one wavefront's slice and
+// the maps)
 bool packed_fits(const cc_plan* P, int32_t B) {
     for (const auto& sp : P->splits) {
+        if (!cc::packed_kernel_split(sp)) continue;
         cc::StepParams h{};
         h.k = P->k;
         h.a = sp.a;
@@ -191,6 +228,8 @@ bool packed_fits(const cc_plan* P, int32_t B) {
         h.Wa = sp.Wa;
         h.Wp = sp.Wp;
         h.Nw = sp.Nw;
+        h.Ws = sp.Ws;
+        h.npairs = sp.npairs;
         h.Cf = sp.Cf;
         h.B = B;
         cc::packed_tile(&h);
@@ -575,13 +614,23 @@ cc_status cc_count_packed(const cc_plan* P, const cc_graph* G, const uint8_t* co
     if (e == hipSuccess && P->splits.empty()) e = cc::launch_fill_f64(root_out, n * B, 1.0, st);
     for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
         const cc::Split& sp = P->splits[i];
-        cc::StepParams h = packed_step_params(P, G, sp, cpk, arena, L, partial, root_out, B);
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
         if (P->profiling) {
             for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
             if (e == hipSuccess) e = hipEventRecord(ev[0], st);
         }
-        if (e == hipSuccess) e = cc::launch_packed_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
+        if (cc::packed_kernel_split(sp)) {
+            cc::StepParams h = packed_step_params(P, G, sp, cpk, arena, L, partial, root_out, B);
+            if (e == hipSuccess) e = cc::launch_packed_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
+        } else {
+            // wide rows: the one-colouring kernels, colouring after colouring (they share the
+            // chunk-partial scratch, so they run in stream order)
+            for (int32_t b = 0; e == hipSuccess && b < B; ++b) {
+                cc::StepParams h = packed_one_params(P, G, sp, colours_dev, arena, L, partial, root_out, B, b);
+                e = cc::launch_split(h, G->n_cu, st, nullptr);
+            }
+            if (e == hipSuccess && P->profiling) e = hipEventRecord(ev[1], st);
+        }
         if (e == hipSuccess && P->profiling) {
             e = hipEventRecord(ev[2], st);
             auto& pe = P->prof_events[i];

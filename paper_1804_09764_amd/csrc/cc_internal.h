@@ -93,17 +93,29 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
 
 int pad_stride(int W);
 
-// Table arena of a packed count with B colourings per row: the plan's allocation sequence replayed
-// with rows of B * W doubles (row stride rounded up to 16 doubles). Returns the arena width in
-// columns; col_off[t] and stride[t] per table.
-int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off, std::vector<int64_t>* stride);
+// Tables of a packed count (B colourings). A narrow table (W <= 64 entries per colouring) is
+// interleaved: row v holds the B entry blocks of v side by side, [v][b][W], row stride rounded up
+// to 16 doubles. A wide table is colouring-major, [b][v][W rounded up to 16], i.e. B one-colouring
+// tables one after another, which the one-colouring kernels read exactly as they read a plain
+// table.
+inline bool packed_wide(int64_t W) { return W > 64; }
 inline int64_t packed_stride(int64_t W) { return (W + 15) / 16 * 16; }
+inline int64_t packed_cols(int64_t W, int B) { return packed_wide(W) ? B * packed_stride(W) : packed_stride(B * W); }
+// The plan's allocation sequence replayed with these table widths (in columns of n_pad doubles).
+// Returns the arena width; col_off[t] per table.
+int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off);
+// Splits of a packed count whose per-colouring rows are all narrow (<= 64 entries) run the packed
+// kernels; wider ones run the one-colouring kernels once per colouring over the packed rows (a
+// wide row already fills the wavefront). The choice depends on the split only, never on B.
+inline bool packed_kernel_split(const Split& sp) {
+    return (sp.p < 2 || sp.Wp <= 64) && sp.Wa <= 64 && sp.Ws <= 64;
+}
 
 // Arguments of one split over one graph and one colouring (shared by host and device code).
 struct StepParams {
     const int64_t* row_ptr;
     const int32_t* col;
-    const uint8_t* colour;
+    const uint8_t* colour;       // colour of vertex u at colour[u * cstride]
     const int32_t* light;        // light rows, heaviest first
     const int32_t* light_start;  // light range r = light[light_start[r] .. light_start[r+1])
     const ChunkItem* chunks;
@@ -116,7 +128,7 @@ struct StepParams {
     const uint16_t* fold;
     const uint32_t* split;
     const uint16_t* mask;        // colour set of each passive entry (over the neighbour's other colours)
-    int64_t pstride, astride, ostride, nstride;
+    int64_t pstride, astride, ostride, nstride, cstride;
     int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
     int lds_wave;       // doubles of LDS per wavefront
     int a_off;          // offset of the staged active row inside the wavefront's LDS slice
@@ -130,6 +142,9 @@ struct StepParams {
     int Cf;             // C(k, p): neighbour-sum entries per colouring, over all k colours
     int tab_u16;        // entries of the block-shared maps at the start of LDS: FM (k * Wp) then E (k * Nw)
     int tab_doubles;    // their size in doubles (rounded up)
+    int pJ;             // tile elements per lane per pass (1, 2, 4, 8)
+    int tg_off;         // offset of the per-lane target table (pJ * k * 64 int16) in a wavefront's slice
+    int cs_off;         // offset of the colour stage of a CSR block (64 * bt bytes)
     const uint16_t* fullmap;  // FM[cu][j] (p >= 2)
     const uint16_t* emap;     // E[cv][q]
 };

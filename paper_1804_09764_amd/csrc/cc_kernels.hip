@@ -118,7 +118,7 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
             const int64_t e = e0 + lane;
             const bool valid = e < end;
             const int u = valid ? S.col[e] : 0;
-            const int cu = valid ? (int)S.colour[u] : 255;
+            const int cu = valid ? (int)S.colour[(int64_t)u * S.cstride] : 255;
             const bool use = valid && cu < k && cu != cv;
             const uint64_t used = __ballot(use);
             const int cnt = __popcll((unsigned long long)used);
@@ -188,7 +188,7 @@ __device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end
         const int64_t e = e0 + lane;
         const bool valid = e < end;
         const int u = valid ? S.col[e] : 0;
-        const int cu = valid ? (int)S.colour[u] : 255;
+        const int cu = valid ? (int)S.colour[(int64_t)u * S.cstride] : 255;
         const bool use = valid && cu < k && cu != cv;
         const uint64_t used = __ballot(use);
         const int cnt = __popcll((unsigned long long)used);
@@ -250,7 +250,7 @@ __device__ void count_colours(const StepParams& S, int64_t beg, int64_t end, int
     for (int64_t e0 = beg; e0 < end; e0 += kWave) {
         const int64_t e = e0 + lane;
         const bool valid = e < end;
-        const int cu = valid ? (int)S.colour[S.col[e]] : 255;
+        const int cu = valid ? (int)S.colour[(int64_t)S.col[e] * S.cstride] : 255;
         for (int c = 0; c < k; ++c) {
             const uint64_t b = __ballot(cu == c);
             if (c == my_c) cnt += (unsigned)__popcll((unsigned long long)b);
@@ -306,7 +306,7 @@ __device__ __forceinline__ void light_row(const StepParams& S, int v, double* N,
     const int64_t beg = S.row_ptr[v];
     const int64_t end = S.row_ptr[v + 1];
     // a vertex without a valid colour (>= k) roots no colourful embedding
-    const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
+    const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[(int64_t)v * S.cstride]);
     if (beg == end || cv >= S.k) {
         double* orow = S.O + (int64_t)v * S.ostride;
         for (int r = lane; r < S.Ws; r += kWave) orow[r] = 0.0;
@@ -327,7 +327,7 @@ __device__ __forceinline__ void do_task(const StepParams& S, int64_t t, double* 
     if (t < S.n_chunks) {
         const ChunkItem ch = S.chunks[t];
         const int v = __builtin_amdgcn_readfirstlane(ch.v);
-        const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[v]);
+        const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[(int64_t)v * S.cstride]);
         for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
         wave_sync_lds();
         if (cv < S.k) {
@@ -389,14 +389,11 @@ __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
 // packed layout: one split for B colourings at once
 // ---------------------------------------------------------------------------------------------
 
-template <int J>
+template <int J, bool P1>
 __global__ __launch_bounds__(256) void k_psplit(StepParams S) {
     extern __shared__ double lds[];
-    uint16_t* tab = reinterpret_cast<uint16_t*>(lds);
-    stage_maps(S, tab);
+    const PMaps M = stage_maps(S, lds);
     __syncthreads();
-    const uint16_t* fml = tab;
-    const uint16_t* eml = tab + (S.p >= 2 ? S.k * S.Wp : 0);
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     double* N = lds + S.tab_doubles + (int64_t)wib * S.lds_wave;
@@ -404,22 +401,20 @@ __global__ __launch_bounds__(256) void k_psplit(StepParams S) {
     const int64_t n_tasks = S.n_chunks + S.n_ranges;
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
     for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves)
-        do_ptask<J>(S, t, N, Ash, fml, eml, lane);
+        do_ptask<J, P1>(S, t, N, Ash, M, lane);
 }
 
 __global__ __launch_bounds__(256) void k_phub(StepParams S) {
     extern __shared__ double lds[];
-    uint16_t* tab = reinterpret_cast<uint16_t*>(lds);
-    stage_maps(S, tab);
+    const PMaps M = stage_maps(S, lds);
     __syncthreads();
-    const uint16_t* eml = tab + (S.p >= 2 ? S.k * S.Wp : 0);
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
     double* N = lds + S.tab_doubles + (int64_t)wib * S.lds_wave;
     double* Ash = N + S.a_off;
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
     for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves)
-        do_phub(S, t, N, Ash, eml, lane);
+        do_phub(S, t, N, Ash, M, lane);
 }
 
 // [B][n] -> [n][B] bytes through 64 x 64 LDS tiles
@@ -876,29 +871,30 @@ hipError_t launch_reduce_batch(const ReduceDesc* rd_dev, int n_inst, int max_blo
 void packed_tile(StepParams* S) {
     const int per = S->Cf + (S->a >= 2 ? S->Wa : 0);
     const int width = S->p >= 2 ? S->Wp : S->k;
-    int bt = S->B < kWave ? S->B : kWave;
+    int cap = S->B < kWave ? S->B : kWave;
     const int by_width = 256 / width > 1 ? 256 / width : 1;  // a tile row of about 2 KB
     const int by_lds = 1024 / per > 1 ? 1024 / per : 1;      // about 8 KB of LDS per wavefront
-    if (bt > by_width) bt = by_width;
-    if (bt > by_lds) bt = by_lds;
-    if (bt < 1) bt = 1;
+    if (cap > by_width) cap = by_width;
+    if (cap > by_lds) cap = by_lds;
+    if (cap < 1) cap = 1;
+    // equal tiles, a multiple of 4 colourings when that stays within the caps
+    const int tiles = (S->B + cap - 1) / cap;
+    int bt = (S->B + tiles - 1) / tiles;
+    if (((bt + 3) & ~3) <= cap) bt = (bt + 3) & ~3;
     S->bt = bt;
+    int J = 1;
+    while (J < 8 && kWave * J < bt * width) J <<= 1;
+    S->pJ = J;
     S->a_off = bt * S->Cf;
-    S->lds_wave = S->a_off + (S->a >= 2 ? bt * S->Wa : 0);
-    S->tab_u16 = (S->p >= 2 ? S->k * S->Wp : 0) + S->k * S->Nw;
+    S->tg_off = S->a_off + (S->a >= 2 ? bt * S->Wa : 0);
+    S->cs_off = S->tg_off + (S->p >= 2 ? J * S->k * kWave / 4 : 0);
+    S->lds_wave = S->cs_off + (kWave * bt + 7) / 8;
+    S->tab_u16 = (S->a >= 2 ? 2 * S->npairs * S->Ws : 0) + (S->p >= 2 ? S->k * S->Wp : 0) + S->k * S->Nw;
     S->tab_doubles = (S->tab_u16 + 3) / 4;
 }
 
 size_t packed_lds_bytes(const StepParams& S, int waves) {
     return ((size_t)S.tab_doubles + (size_t)S.lds_wave * waves) * sizeof(double);
-}
-
-static int packed_J(const StepParams& S) {
-    const int width = S.p >= 2 ? S.Wp : S.k;
-    const int el = S.bt * width;
-    int J = 1;
-    while (J < 8 && kWave * J < el) J <<= 1;
-    return J;
 }
 
 hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) {
@@ -909,11 +905,18 @@ hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_
     S.waves_per_block = w;
     const int threads = w * kWave;
     const size_t lds = packed_lds_bytes(S, w);
-    const int J = packed_J(S);
-    const void* fn = J == 1 ? (const void*)k_psplit<1>
-                   : J == 2 ? (const void*)k_psplit<2>
-                   : J == 4 ? (const void*)k_psplit<4>
-                            : (const void*)k_psplit<8>;
+    const int J = S.pJ;
+    const void* fn;
+    if (S.p == 1)
+        fn = J == 1 ? (const void*)k_psplit<1, true>
+           : J == 2 ? (const void*)k_psplit<2, true>
+           : J == 4 ? (const void*)k_psplit<4, true>
+                    : (const void*)k_psplit<8, true>;
+    else
+        fn = J == 1 ? (const void*)k_psplit<1, false>
+           : J == 2 ? (const void*)k_psplit<2, false>
+           : J == 4 ? (const void*)k_psplit<4, false>
+                    : (const void*)k_psplit<8, false>;
     int per_cu = 0;
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
     if (err != hipSuccess) return err;

@@ -24,59 +24,109 @@
 
 namespace cc {
 
+// block-shared copies of the split's maps in LDS
+struct PMaps {
+    const uint32_t* sp;  // split list [pair][output] (a >= 2)
+    const uint16_t* fm;  // FM[cu][j] (p >= 2)
+    const uint16_t* em;  // E[cv][q]
+};
+
+// Colours of the 64 entries of a CSR block for the tile's colourings, staged in LDS:
+// cs[i * bt + bl] = col_{b0 + bl}(u_i). Lane i copies the colours of its own entry, so a block's
+// colours arrive in one round trip instead of one per entry.
+__device__ inline void stage_colours(const StepParams& S, int uvec, int cnt, int b0, int nb, uint8_t* cs, int lane) {
+    wave_sync_lds();  // earlier reads of the stage are done
+    if (lane < cnt) {
+        const uint8_t* src = S.colour + (int64_t)uvec * S.B + b0;
+        uint8_t* dst = cs + lane * S.bt;
+        if (((S.B | b0 | nb | S.bt) & 3) == 0) {  // 4-byte aligned: four colourings per load
+            for (int q = 0; q < nb; q += 4)
+                *reinterpret_cast<uint32_t*>(dst + q) = *reinterpret_cast<const uint32_t*>(src + q);
+        } else {
+            for (int q = 0; q < nb; ++q) dst[q] = src[q];
+        }
+    }
+    wave_sync_lds();
+}
+
+// rows of entries [g D, g D + D) of a block in flight: values and N targets (-1: nothing to add)
+template <int J, int D>
+__device__ __forceinline__ void pload(const StepParams& S, int g, int cnt, int uvec, const uint8_t* cs, const int (&bl)[J],
+                                      const int16_t* tg, const double* Pt, double (&X)[D][J], int (&F)[D][J], int lane) {
+    const int k = S.k;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        const int i = g * D + q;
+        const bool live = i < cnt;
+        const int u = bcast(uvec, live ? i : 0);
+#pragma unroll
+        for (int t = 0; t < J; ++t) {
+            const int cu = live ? (int)cs[i * S.bt + bl[t]] : 255;
+            F[q][t] = cu < k ? (int)tg[(t * k + cu) * kWave + lane] : -1;
+            X[q][t] = F[q][t] >= 0 ? Pt[(int64_t)u * S.pstride + kWave * t] : 0.0;
+        }
+    }
+}
+
+// N[F] += X for the group, in (entry, element) order. An LDS add without return (ds_add_f64) keeps
+// the wavefront from waiting on a read of N; a wavefront's LDS operations complete in issue order
+// and the targets of one instruction are distinct, so every entry still receives its terms in
+// CSR order.
+template <int J, int D>
+__device__ __forceinline__ void padd(double* N, const double (&X)[D][J], const int (&F)[D][J]) {
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int t = 0; t < J; ++t)
+            if (F[q][t] >= 0) __hip_atomic_fetch_add(N + F[q][t], X[q][t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // neighbour sum of CSR entries [beg, end) for the tile's colourings, p >= 2; cvrow = col_b(v) for
-// the tile's colourings, fml = FM in LDS
+// the tile's colourings, fml = FM in LDS, tg = this wavefront's target table (J * k * 64 entries),
+// cs = its colour stage (64 * bt bytes)
 template <int J>
 __device__ void pgather(const StepParams& S, int64_t beg, int64_t end, const uint8_t* cvrow, int b0, int nb,
-                        double* N, const uint16_t* fml, int lane) {
-    constexpr int D = (J >= 8) ? 2 : 4;  // neighbours in flight per wavefront
-    const int k = S.k, Wp = S.Wp, B = S.B, Cf = S.Cf;
+                        double* N, const uint16_t* fml, int16_t* tg, uint8_t* cs, int lane) {
+    constexpr int D = 8 / J;  // entries per group; two groups (16 loads per lane) are in flight
+    const int k = S.k, Wp = S.Wp, Cf = S.Cf;
     const int E = nb * Wp;
-    const uint8_t* cp = S.colour + b0;
     for (int c0 = 0; c0 < E; c0 += kWave * J) {
-        // element f = c0 + lane + 64 t of the tile: colouring b0 + bl, passive entry jj
-        int bl[J], jj[J], cvt[J], msk[J];
+        // element f = c0 + lane + 64 t of the tile is (colouring b0 + bl, passive entry jj). Its
+        // N target for a neighbour of colour c depends only on c: tabulate it per lane,
+        // tg[(t k + c) 64 + lane] = bl Cf + FM[c][jj], or -1 when the entry is of no use to v
+        // (c = col_b(v), or the entry's set holds col_b(v), or v has no valid colour)
+        int bl[J];
 #pragma unroll
         for (int t = 0; t < J; ++t) {
             const int f = c0 + lane + kWave * t;
             const bool ok = f < E;
             bl[t] = ok ? f / Wp : 0;
-            jj[t] = ok ? f - bl[t] * Wp : 0;
-            const int c = ok ? (int)cvrow[bl[t]] : 255;
-            cvt[t] = c < k ? c : 255;  // 255: no valid colour, the element never contributes
-            msk[t] = ok ? (int)S.mask[jj[t]] : 0xFFFF;
+            const int jj = ok ? f - bl[t] * Wp : 0;
+            const int cv = ok ? (int)cvrow[bl[t]] : 255;
+            const int msk = ok ? (int)S.mask[jj] : 0xFFFF;
+            for (int c = 0; c < k; ++c) {
+                const bool valid = cv < k && c != cv;
+                const int xpos = valid ? cv - (cv > c ? 1 : 0) : 0;
+                const bool need = valid && ((msk >> xpos) & 1) == 0;
+                tg[(t * k + c) * kWave + lane] = need ? (int16_t)(bl[t] * Cf + (int)fml[c * Wp + jj]) : (int16_t)-1;
+            }
         }
         const double* Pt = S.P + (int64_t)b0 * Wp + c0 + lane;
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int64_t e = e0 + lane;
             const int uvec = e < end ? S.col[e] : 0;
             const int cnt = (end - e0 < kWave) ? (int)(end - e0) : kWave;
-            for (int i = 0; i < cnt; i += D) {
-                int cb[D], uq[D];
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    const bool live = i + q < cnt;
-                    uq[q] = bcast(uvec, live ? i + q : 0);
-                    cb[q] = (live && lane < nb) ? (int)cp[(int64_t)uq[q] * B + lane] : 255;
-                }
-                double x[D][J];
-                int dst[D][J];
-#pragma unroll
-                for (int q = 0; q < D; ++q)
-#pragma unroll
-                    for (int t = 0; t < J; ++t) {
-                        const int cu = __shfl(cb[q], bl[t]);
-                        const bool valid = cu < k && cvt[t] < k && cu != cvt[t];
-                        const int xpos = valid ? cvt[t] - (cvt[t] > cu ? 1 : 0) : 0;
-                        const bool need = valid && ((msk[t] >> xpos) & 1) == 0;
-                        dst[q][t] = need ? bl[t] * Cf + (int)fml[cu * Wp + jj[t]] : -1;
-                        x[q][t] = need ? Pt[(int64_t)uq[q] * S.pstride + kWave * t] : 0.0;
-                    }
-#pragma unroll
-                for (int q = 0; q < D; ++q)
-#pragma unroll
-                    for (int t = 0; t < J; ++t)
-                        if (dst[q][t] >= 0) N[dst[q][t]] += x[q][t];
+            stage_colours(S, uvec, cnt, b0, nb, cs, lane);
+            const int ng = (cnt + D - 1) / D;
+            double XA[D][J], XB[D][J];
+            int FA[D][J], FB[D][J];
+            pload<J, D>(S, 0, cnt, uvec, cs, bl, tg, Pt, XA, FA, lane);
+            for (int g = 0; g < ng; g += 2) {
+                if (g + 1 < ng) pload<J, D>(S, g + 1, cnt, uvec, cs, bl, tg, Pt, XB, FB, lane);
+                padd<J, D>(N, XA, FA);
+                if (g + 1 >= ng) break;
+                if (g + 2 < ng) pload<J, D>(S, g + 2, cnt, uvec, cs, bl, tg, Pt, XA, FA, lane);
+                padd<J, D>(N, XB, FB);
             }
         }
     }
@@ -84,11 +134,10 @@ __device__ void pgather(const StepParams& S, int64_t beg, int64_t end, const uin
 
 // p = 1: N[bl * k + c] += number of entries in [beg, end) whose colour under colouring b0 + bl is c
 template <int J>
-__device__ void pcount(const StepParams& S, int64_t beg, int64_t end, int b0, int nb, double* N, int lane) {
-    constexpr int D = 4;
-    const int k = S.k, B = S.B, Cf = S.Cf;
+__device__ void pcount(const StepParams& S, int64_t beg, int64_t end, int b0, int nb, double* N, uint8_t* cs,
+                       int lane) {
+    const int k = S.k, Cf = S.Cf;
     const int E = nb * k;
-    const uint8_t* cp = S.colour + b0;
     for (int c0 = 0; c0 < E; c0 += kWave * J) {
         int bl[J], ct[J];
         unsigned cnt_t[J];
@@ -104,19 +153,10 @@ __device__ void pcount(const StepParams& S, int64_t beg, int64_t end, int b0, in
             const int64_t e = e0 + lane;
             const int uvec = e < end ? S.col[e] : 0;
             const int cnt = (end - e0 < kWave) ? (int)(end - e0) : kWave;
-            for (int i = 0; i < cnt; i += D) {
-                int cb[D];
+            stage_colours(S, uvec, cnt, b0, nb, cs, lane);
+            for (int i = 0; i < cnt; ++i)
 #pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    const bool live = i + q < cnt;
-                    const int u = bcast(uvec, live ? i + q : 0);
-                    cb[q] = (live && lane < nb) ? (int)cp[(int64_t)u * B + lane] : 255;
-                }
-#pragma unroll
-                for (int q = 0; q < D; ++q)
-#pragma unroll
-                    for (int t = 0; t < J; ++t) cnt_t[t] += (__shfl(cb[q], bl[t]) == ct[t]) ? 1u : 0u;
-            }
+                for (int t = 0; t < J; ++t) cnt_t[t] += ((int)cs[i * S.bt + bl[t]] == ct[t]) ? 1u : 0u;
         }
 #pragma unroll
         for (int t = 0; t < J; ++t)
@@ -126,7 +166,8 @@ __device__ void pcount(const StepParams& S, int64_t beg, int64_t end, int b0, in
 
 // output rows of v for the tile's colourings from N (LDS) and v's active rows
 __device__ inline void pcombine(const StepParams& S, int v, const uint8_t* cvrow, int b0, int nb, const double* N,
-                                double* Ash, const uint16_t* eml, int lane) {
+                                double* Ash, const PMaps& M, int lane) {
+    const uint16_t* eml = M.em;
     const int k = S.k, Ws = S.Ws, Cf = S.Cf, Nw = S.Nw;
     double* orow = S.O + (int64_t)v * S.ostride + (int64_t)b0 * Ws;
     const int E = nb * Ws;
@@ -140,7 +181,20 @@ __device__ inline void pcombine(const StepParams& S, int v, const uint8_t* cvrow
         return;
     }
     const double* arow = S.A + (int64_t)v * S.astride + (int64_t)b0 * S.Wa;
-    for (int i = lane; i < nb * S.Wa; i += kWave) Ash[i] = arow[i];
+    const int na = nb * S.Wa;
+    for (int i0 = 0; i0 < na; i0 += 4 * kWave) {  // four loads in flight per lane
+        double a4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + q * kWave + lane;
+            a4[q] = i < na ? arow[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + q * kWave + lane;
+            if (i < na) Ash[i] = a4[q];
+        }
+    }
     wave_sync_lds();
     for (int f = lane; f < E; f += kWave) {
         const int bl = f / Ws, r = f - bl * Ws;
@@ -150,7 +204,7 @@ __device__ inline void pcombine(const StepParams& S, int v, const uint8_t* cvrow
             const double* Ab = Ash + bl * S.Wa;
             const double* Nb = N + bl * Cf;
             const uint16_t* eb = eml + cv * Nw;
-            const uint32_t* sp = S.split + r;
+            const uint32_t* sp = M.sp + r;
             for (int j = 0; j < S.npairs; ++j) {
                 const uint32_t pr = sp[(int64_t)j * Ws];
                 sum += Ab[pr & 0xFFFFu] * Nb[eb[pr >> 16]];
@@ -160,16 +214,18 @@ __device__ inline void pcombine(const StepParams& S, int v, const uint8_t* cvrow
     }
 }
 
-template <int J>
+// P1: the split's passive part is a single vertex (p = 1)
+template <int J, bool P1>
 __device__ __forceinline__ void pneighbours(const StepParams& S, int64_t beg, int64_t end, const uint8_t* cvrow, int b0,
-                                            int nb, double* N, const uint16_t* fml, int lane) {
-    if (S.p == 1) pcount<J>(S, beg, end, b0, nb, N, lane);
-    else pgather<J>(S, beg, end, cvrow, b0, nb, N, fml, lane);
+                                            int nb, double* N, const PMaps& M, int lane) {
+    const uint16_t* fml = M.fm;
+    uint8_t* cs = reinterpret_cast<uint8_t*>(N + S.cs_off);
+    if constexpr (P1) pcount<J>(S, beg, end, b0, nb, N, cs, lane);
+    else pgather<J>(S, beg, end, cvrow, b0, nb, N, fml, reinterpret_cast<int16_t*>(N + S.tg_off), cs, lane);
 }
 
-template <int J>
-__device__ void plight_row(const StepParams& S, int v, double* N, double* Ash, const uint16_t* fml,
-                           const uint16_t* eml, int lane) {
+template <int J, bool P1>
+__device__ void plight_row(const StepParams& S, int v, double* N, double* Ash, const PMaps& M, int lane) {
     const int64_t beg = S.row_ptr[v];
     const int64_t end = S.row_ptr[v + 1];
     const uint8_t* cvall = S.colour + (int64_t)v * S.B;
@@ -177,17 +233,16 @@ __device__ void plight_row(const StepParams& S, int v, double* N, double* Ash, c
         const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
         for (int i = lane; i < nb * S.Cf; i += kWave) N[i] = 0.0;
         wave_sync_lds();
-        if (beg < end) pneighbours<J>(S, beg, end, cvall + b0, b0, nb, N, fml, lane);
+        if (beg < end) pneighbours<J, P1>(S, beg, end, cvall + b0, b0, nb, N, M, lane);
         wave_sync_lds();
-        pcombine(S, v, cvall + b0, b0, nb, N, Ash, eml, lane);
+        pcombine(S, v, cvall + b0, b0, nb, N, Ash, M, lane);
         wave_sync_lds();
     }
 }
 
 // task t: a chunk of a cut row (partial rows of all colourings to scratch) or a range of light rows
-template <int J>
-__device__ void do_ptask(const StepParams& S, int64_t t, double* N, double* Ash, const uint16_t* fml,
-                         const uint16_t* eml, int lane) {
+template <int J, bool P1>
+__device__ void do_ptask(const StepParams& S, int64_t t, double* N, double* Ash, const PMaps& M, int lane) {
     if (t < S.n_chunks) {
         const ChunkItem ch = S.chunks[t];
         const int v = __builtin_amdgcn_readfirstlane(ch.v);
@@ -197,7 +252,7 @@ __device__ void do_ptask(const StepParams& S, int64_t t, double* N, double* Ash,
             const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
             for (int i = lane; i < nb * S.Cf; i += kWave) N[i] = 0.0;
             wave_sync_lds();
-            pneighbours<J>(S, ch.beg, ch.beg + ch.len, cvall + b0, b0, nb, N, fml, lane);
+            pneighbours<J, P1>(S, ch.beg, ch.beg + ch.len, cvall + b0, b0, nb, N, M, lane);
             wave_sync_lds();
             for (int i = lane; i < nb * S.Cf; i += kWave) prow[(int64_t)b0 * S.Cf + i] = N[i];
             wave_sync_lds();
@@ -205,12 +260,12 @@ __device__ void do_ptask(const StepParams& S, int64_t t, double* N, double* Ash,
     } else {
         const int64_t r = t - S.n_chunks;
         const int i0 = S.light_start[r], i1 = S.light_start[r + 1];
-        for (int i = i0; i < i1; ++i) plight_row<J>(S, S.light[i], N, Ash, fml, eml, lane);
+        for (int i = i0; i < i1; ++i) plight_row<J, P1>(S, S.light[i], N, Ash, M, lane);
     }
 }
 
 // cut row t: chunk partials added in chunk order, then the combine
-__device__ inline void do_phub(const StepParams& S, int64_t t, double* N, double* Ash, const uint16_t* eml, int lane) {
+__device__ inline void do_phub(const StepParams& S, int64_t t, double* N, double* Ash, const PMaps& M, int lane) {
     const HubItem h = S.hubs[t];
     const uint8_t* cvall = S.colour + (int64_t)h.v * S.B;
     for (int b0 = 0; b0 < S.B; b0 += S.bt) {
@@ -222,16 +277,23 @@ __device__ inline void do_phub(const StepParams& S, int64_t t, double* N, double
             N[i] = sum;
         }
         wave_sync_lds();
-        pcombine(S, h.v, cvall + b0, b0, nb, N, Ash, eml, lane);
+        pcombine(S, h.v, cvall + b0, b0, nb, N, Ash, M, lane);
         wave_sync_lds();
     }
 }
 
-// block-shared maps: FM (p >= 2) then E, copied from the plan constants
-__device__ inline void stage_maps(const StepParams& S, uint16_t* tab) {
+// block-shared maps, copied from the plan constants: the split list (a >= 2, u32), then FM
+// (p >= 2) and E (u16)
+__device__ inline PMaps stage_maps(const StepParams& S, void* lds) {
+    uint32_t* sp = reinterpret_cast<uint32_t*>(lds);
+    const int nsp = S.a >= 2 ? S.npairs * S.Ws : 0;
+    uint16_t* fm = reinterpret_cast<uint16_t*>(sp + nsp);
     const int nfm = S.p >= 2 ? S.k * S.Wp : 0;
-    for (int i = threadIdx.x; i < nfm; i += blockDim.x) tab[i] = S.fullmap[i];
-    for (int i = threadIdx.x; i < S.k * S.Nw; i += blockDim.x) tab[nfm + i] = S.emap[i];
+    uint16_t* em = fm + nfm;
+    for (int i = threadIdx.x; i < nsp; i += blockDim.x) sp[i] = S.split[i];
+    for (int i = threadIdx.x; i < nfm; i += blockDim.x) fm[i] = S.fullmap[i];
+    for (int i = threadIdx.x; i < S.k * S.Nw; i += blockDim.x) em[i] = S.emap[i];
+    return PMaps{sp, fm, em};
 }
 
 }  // namespace cc

@@ -298,18 +298,14 @@ Schedule schedule(int k, const Rooted& R, int root) {
 
 }  // namespace
 
-int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off, std::vector<int64_t>* stride) {
+int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off) {
     // the allocation order of schedule(): each split allocates its output table, then releases
     // its active and passive inputs
     Arena A;
     col_off->assign(P->tables.size(), 0);
-    stride->assign(P->tables.size(), 0);
     for (const Split& sp : P->splits) {
-        if (sp.out >= 0) {
-            const int64_t w = packed_stride((int64_t)B * P->tables[(size_t)sp.out].W);
-            (*stride)[(size_t)sp.out] = w;
-            (*col_off)[(size_t)sp.out] = A.alloc(w);
-        }
+        if (sp.out >= 0)
+            (*col_off)[(size_t)sp.out] = A.alloc(packed_cols(P->tables[(size_t)sp.out].W, B));
         if (sp.act >= 0) A.release((*col_off)[(size_t)sp.act]);
         if (sp.pas >= 0) A.release((*col_off)[(size_t)sp.pas]);
     }
