@@ -83,6 +83,26 @@ def loaded_bytes(k, s, a, p, n, nnz):
     return b
 
 
+def loaded_bytes_packed(k, s, a, p, n, nnz, B):
+    """Algorithmic bytes of one packed launch (all B colourings of a split at once): per CSR entry
+    the column (4 B), the neighbour's B colours (B bytes) and, when p >= 2, the neighbour's tile
+    rows of 8 B C(k-1, p-1) per colouring, read for the fraction (k-1)/k of colourings in which
+    the neighbour's colour differs from the row's; per vertex its row offsets, B colours, B active
+    rows (a >= 2) and B output rows."""
+    Wp, Wa, Ws = widths(k, s, a, p)
+    b = (4 + B) * nnz + 8 * (n + 1) + B * n + 8 * B * n * Ws + (8 * B * n * Wa if a >= 2 else 0)
+    if p >= 2:
+        b += 8 * B * Wp * nnz * (k - 1) / k
+    return b
+
+
+def packed_kernel_split(k, s, a, p):
+    """Whether a packed count runs this split on packed rows (every per-colouring width <= 64) or
+    colouring by colouring with the one-colouring kernels."""
+    Wp, Wa, Ws = widths(k, s, a, p)
+    return (p < 2 or Wp <= 64) and Wa <= 64 and Ws <= 64
+
+
 def load_traffic(workload: str, split_index: int):
     """HBM traffic per launch (GB) of the dominant kernel from committed rocprofv3 counters, or None
     if they were taken on another kernel source."""
@@ -174,9 +194,32 @@ def bench(args):
     print(f"[bench] plan root={P.info.root} splits={P.splits} workspace={ws_bytes / 1e9:.2f} GB "
           f"graph={G.info}", file=sys.stderr, flush=True)
 
+    packed = args.path in ("packed", "auto")
+    pack = B
+    if packed:
+        # colourings per packed count: all of the step's if their tables fit in HBM next to the
+        # graph, else the largest power-of-two share that does (the counts run one after another
+        # and reuse the workspace)
+        free = torch.cuda.mem_get_info(dev)[0]
+        while pack > 1 and cc.count_packed_workspace_bytes(P, G, pack) > 0.85 * free:
+            pack //= 2
+        if args.path == "auto" and (pack < B or B < 8):
+            # packed rows pay off from about 8 colourings per count; below that, and when the
+            # step's colourings do not fit in one packed count, the one-colouring path is faster
+            packed = False
+            ws_bytes = cc.count_workspace_bytes(P, G)
+        else:
+            ws_bytes = cc.count_packed_workspace_bytes(P, G, pack)
+            print(f"[bench] packed counts of {pack} colourings, workspace {ws_bytes / 1e9:.2f} GB",
+                  file=sys.stderr, flush=True)
+
     def step(i):
         cc.colour(G, k, seed=args.seed, first_iter=i * B, B=B, out=colours)
-        cc.count(P, G, colours, workspace=ws, out=X)
+        if packed:
+            for c0 in range(0, B, pack):
+                cc.count_packed(P, G, colours[c0:c0 + pack], workspace=ws, out=X[c0:c0 + pack])
+        else:
+            cc.count(P, G, colours, workspace=ws, out=X)
 
     for i in range(args.warmup):
         step(i)
@@ -201,9 +244,10 @@ def bench(args):
     dom = int(np.argmax(gather_ms))
     s, a, p = P.splits[dom]
     avg_ms = gather_ms[dom] / max(1, launches[dom])
-    alg = loaded_bytes(k, s, a, p, n, nnz)
+    dom_packed = packed and packed_kernel_split(k, s, a, p)
+    alg = loaded_bytes_packed(k, s, a, p, n, nnz, pack) if dom_packed else loaded_bytes(k, s, a, p, n, nnz)
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload, dom)
+    traffic = None if dom_packed else load_traffic(args.workload, dom)
     per_split = [{"s": S, "a": A, "p": Pp, "gather_ms": round(float(g) / max(1, c), 4),
                   "finish_ms": round(float(f) / max(1, c), 4)}
                  for (S, A, Pp), g, f, c in zip(P.splits, gather_ms, finish_ms, launches)]
@@ -223,11 +267,13 @@ def bench(args):
         "config": {"workload": args.workload, "graph": f"R-MAT scale {W['scale']} edge factor {W['ef']} "
                    f"(a,b,c)=(0.57,0.19,0.19) seed {W['gseed']}", "n": n, "nnz": nnz,
                    "template": f"Pruefer tree k={k} seed {W['tseed']}", "colourings_per_step": B,
-                   "units_per_edge": units_per_edge, "path": "plain"},
+                   "units_per_edge": units_per_edge, "path": "packed" if packed else "plain",
+                   "colourings_per_packed_count": pack if packed else None,
+                   "workspace_GB": ws_bytes / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": f"k_split split {dom} (s={s}, a={a}, p={p})",
+                     "kernel": f"{'k_psplit' if dom_packed else 'k_split'} split {dom} (s={s}, a={a}, p={p})",
                      "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg,
                      "compulsory_bytes_per_launch": split_bytes(k, s, a, p, n, nnz),
@@ -255,10 +301,15 @@ def bench(args):
 
 def batched_vs_plain(args, reps: int = 2):
     """Plain vs batched on the batched configuration: R-MAT scale 18 (edge factor 16, seed 2), all
-    11 trees with 7 vertices x 64 colourings. Plain = one cc_count call per tree over the 64
-    colourings (colourings and splits run one after another); batched = the 704 instances in one
-    persistent launch (and, for reference, one launch per dependency level). Results must agree
-    bit for bit."""
+    11 trees with 7 vertices x 64 colourings.
+
+    plain   = one cc_count call per tree: colourings and splits one after another, one table row
+              per (vertex, colouring);
+    batched = one cc_count_packed call per tree: the 64 colourings share every table row and every
+              pass over the graph (exact below 2^53, 1e-12 relative above, against plain);
+    instances_persistent / instances_levels = the 704 (tree, colouring) instances in one persistent
+              launch / one launch per dependency level (bit-identical to plain)."""
+    import numpy as np
     import torch
 
     import inputs
@@ -280,13 +331,21 @@ def batched_vs_plain(args, reps: int = 2):
         for t, P in enumerate(plans):
             cc.count(P, G, C, workspace=ws, out=Xp[t])
 
+    Xk = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
+    wsk = cc.Workspace()
+
+    def packed():
+        for t, P in enumerate(plans):
+            cc.count_packed(P, G, C, workspace=wsk, out=Xk[t])
+
     Xb = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
     inst = [(P, G, C[b], Xb[t, b:b + 1], None) for t, P in enumerate(plans) for b in range(B)]
     persistent = cc.Batch(inst)
     levels = cc.Batch(inst, levels=True)
     wsb = cc.Workspace()
     res = {}
-    for name, fn in (("plain", plain), ("batched", lambda: persistent.run(wsb)), ("levels", lambda: levels.run(wsb))):
+    for name, fn in (("plain", plain), ("batched", packed), ("instances_persistent", lambda: persistent.run(wsb)),
+                     ("instances_levels", lambda: levels.run(wsb))):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -294,21 +353,33 @@ def batched_vs_plain(args, reps: int = 2):
             fn()
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) / reps
-        if name != "plain":
-            if name == "batched":
-                persistent.check()
-            same = bool(torch.equal(Xb, Xp))
-            res[name + "_equal"] = same
+        print(f"[bench] {name}: {res[name] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        if name == "instances_persistent":
+            persistent.check()
+        if name.startswith("instances"):
+            res[name + "_equal"] = bool(torch.equal(Xb, Xp))
+    xp, xk = Xp.cpu().numpy(), Xk.cpu().numpy()
+    small = xp < 2.0 ** 53
+    packed_ok = bool(np.array_equal(xk[small], xp[small]) and
+                     (np.all(np.abs(xk[~small] - xp[~small]) <= 1e-12 * xp[~small]) if (~small).any() else True))
     return {"workload": "rmat18-ef16-trees7x64",
             "graph": "R-MAT scale 18 edge factor 16 seed 2", "n": n, "nnz": nnz,
             "templates": "all 11 trees with 7 vertices", "colourings": B, "instances": len(inst),
             "units": units,
             "plain": {"value": units / res["plain"], "ms": res["plain"] * 1e3},
             "batched": {"value": units / res["batched"], "ms": res["batched"] * 1e3,
-                        "equal_to_plain": res["batched_equal"], "launch": "one persistent launch"},
-            "levels": {"value": units / res["levels"], "ms": res["levels"] * 1e3,
-                       "equal_to_plain": res["levels_equal"], "launch": "one launch per dependency level"},
-            "workspace_GB": persistent.workspace_bytes / 1e9}
+                        "speedup_vs_plain": res["plain"] / res["batched"],
+                        "matches_plain": packed_ok, "above_2_53": int((~small).sum()),
+                        "launch": "one packed count per tree: 64 colourings per table row"},
+            "instances_persistent": {"value": units / res["instances_persistent"],
+                                     "ms": res["instances_persistent"] * 1e3,
+                                     "equal_to_plain": res["instances_persistent_equal"],
+                                     "launch": "704 instances, one persistent launch"},
+            "instances_levels": {"value": units / res["instances_levels"], "ms": res["instances_levels"] * 1e3,
+                                 "equal_to_plain": res["instances_levels_equal"],
+                                 "launch": "704 instances, one launch per dependency level"},
+            "workspace_GB": {"batched": cc.count_packed_workspace_bytes(plans[0], G, B) / 1e9,
+                             "instances": persistent.workspace_bytes / 1e9}}
 
 
 SERVE_POOL = [(16 + (i % 7), (8, 16, 32)[i % 3], 100 + i) for i in range(16)]  # (scale, edge factor, seed)
@@ -461,6 +532,10 @@ def main():
     ap.add_argument("--seed", type=int, default=777)
     ap.add_argument("--hub-threshold", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--path", default="auto", choices=("auto", "packed", "plain"),
+                    help="packed: the colourings of a step share the table rows (cc_count_packed); "
+                         "plain: one colouring after another (cc_count); auto: packed when the step has "
+                         "at least 8 colourings and they fit in one packed count, else plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the plain-vs-batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")

@@ -209,6 +209,9 @@ cc_status cc_count_packed_workspace_bytes(const cc_plan* plan, const cc_graph* g
 cc_status cc_count_packed(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
                           void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
 
+/* Synchronise `stream` and report any device error of the work queued on it (CC_EDEVICE). */
+cc_status cc_stream_check(void* stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Batched count: many colourings and templates, on one or more graphs, in one launch          */
 /* (the independent outer iterations of Algorithm 1 run together)                              */
@@ -260,17 +263,19 @@ void cc_batch_destroy(cc_batch* batch);
 /* ------------------------------------------------------------------------------------------ */
 
 /*
- * Per-split kernel timing. While enabled on a plan, every cc_count with that plan records HIP
- * events on its stream around (1) the neighbour-gather + combine kernel and (2) the cut-row finish
- * kernel of each split, for every colouring. Not thread-safe: one counting stream per plan while
- * enabled. Enabling again clears what was recorded.
+ * Per-split kernel timing. While enabled on a plan, every cc_count and cc_count_packed with that
+ * plan records HIP events on its stream around (1) the neighbour-gather + combine kernel and (2)
+ * the cut-row finish kernel of each split, for every launch: one per colouring for cc_count and
+ * for the splits a packed count runs colouring by colouring, one per packed count for the splits
+ * it runs on packed rows. Not thread-safe: one counting stream per plan while enabled. Enabling
+ * again clears what was recorded.
  */
 cc_status cc_profile_enable(cc_plan* plan, int32_t enable);
 
 /*
  * Synchronise on the recorded events and return, for each of the first n splits (execution
  * order), the summed milliseconds of its gather kernel and of its finish kernel and the number of
- * colourings recorded. Any array may be NULL. Recording stays enabled and is cleared.
+ * launches recorded. Any array may be NULL. Recording stays enabled and is cleared.
  */
 cc_status cc_profile_read(cc_plan* plan, int32_t n, double* gather_ms_host, double* finish_ms_host,
                           int64_t* launches_host);

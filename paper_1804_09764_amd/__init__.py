@@ -72,7 +72,7 @@ class _Tuning(ctypes.Structure):
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
            "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
-           "cc_count_packed_workspace_bytes", "cc_count_packed",
+           "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check",
            "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read",
            "cc_batch_create", "cc_batch_workspace_bytes", "cc_batch_run", "cc_batch_check", "cc_batch_destroy"]
 
@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "cc_count": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
+        "cc_stream_check": (ctypes.c_int, [P]),
         "cc_estimate": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
         "cc_estimate_median_of_means": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ctypes.c_double)]),
@@ -343,6 +344,11 @@ def count_packed(plan: Plan, graph: Graph, colours, per_vertex: bool = False, wo
                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dev_ptr(X, torch.float64, "X"),
                                  _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
     return (X, V) if per_vertex else X
+
+
+def stream_check(stream=None):
+    """Synchronise `stream` (default: the current one) and raise CCError on a device error."""
+    _check(lib().cc_stream_check(_stream(stream)))
 
 
 def estimate(plan: Plan, X) -> tuple[float, float]:

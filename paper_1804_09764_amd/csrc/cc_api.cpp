@@ -614,30 +614,32 @@ cc_status cc_count_packed(const cc_plan* P, const cc_graph* G, const uint8_t* co
     if (e == hipSuccess && P->splits.empty()) e = cc::launch_fill_f64(root_out, n * B, 1.0, st);
     for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
         const cc::Split& sp = P->splits[i];
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        if (P->profiling) {
-            for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
-            if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-        }
-        if (cc::packed_kernel_split(sp)) {
-            cc::StepParams h = packed_step_params(P, G, sp, cpk, arena, L, partial, root_out, B);
-            if (e == hipSuccess) e = cc::launch_packed_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
-        } else {
-            // wide rows: the one-colouring kernels, colouring after colouring (they share the
-            // chunk-partial scratch, so they run in stream order)
-            for (int32_t b = 0; e == hipSuccess && b < B; ++b) {
-                cc::StepParams h = packed_one_params(P, G, sp, colours_dev, arena, L, partial, root_out, B, b);
-                e = cc::launch_split(h, G->n_cu, st, nullptr);
+        // wide rows run the one-colouring kernels colouring after colouring (they share the
+        // chunk-partial scratch, so they run in stream order); each launch pair is timed alone
+        const bool packed_k = cc::packed_kernel_split(sp);
+        for (int32_t b = 0; e == hipSuccess && b < (packed_k ? 1 : B); ++b) {
+            hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+            if (P->profiling) {
+                for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+                if (e == hipSuccess) e = hipEventRecord(ev[0], st);
             }
-            if (e == hipSuccess && P->profiling) e = hipEventRecord(ev[1], st);
-        }
-        if (e == hipSuccess && P->profiling) {
-            e = hipEventRecord(ev[2], st);
-            auto& pe = P->prof_events[i];
-            pe.push_back(ev[0]);
-            pe.push_back(ev[1]);
-            pe.push_back(ev[2]);
-            P->prof_launches[i] += 1;
+            if (e == hipSuccess) {
+                if (packed_k) {
+                    cc::StepParams h = packed_step_params(P, G, sp, cpk, arena, L, partial, root_out, B);
+                    e = cc::launch_packed_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
+                } else {
+                    cc::StepParams h = packed_one_params(P, G, sp, colours_dev, arena, L, partial, root_out, B, b);
+                    e = cc::launch_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
+                }
+            }
+            if (e == hipSuccess && P->profiling) {
+                e = hipEventRecord(ev[2], st);
+                auto& pe = P->prof_events[i];
+                pe.push_back(ev[0]);
+                pe.push_back(ev[1]);
+                pe.push_back(ev[2]);
+                P->prof_launches[i] += 1;
+            }
         }
     }
     if (e == hipSuccess) e = cc::launch_reduce_packed(root_out, n, B, red, X_dev, st);
@@ -859,6 +861,13 @@ cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream)
         if (B->inst[i].in.graph->n == 0) e = cc::launch_fill_f64(B->inst[i].in.X_dev, 1, 0.0, st);
     if (e == hipSuccess) e = cc::launch_reduce_batch(rd_dev, (int)B->inst.size(), B->max_red_blocks, st);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return CC_OK;
+}
+
+cc_status cc_stream_check(void* stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "stream check");
     return CC_OK;
 }
 

@@ -68,7 +68,7 @@ class Slot:
 class Executor:
     """What the server needs from a device."""
 
-    def slot_bytes(self, req: Request) -> int:  # memory of one colouring of `req`
+    def slot_bytes(self, req: Request, count: int = 1) -> int:  # memory of `count` colourings of `req`
         raise NotImplementedError
 
     def launch(self, slots: list[Slot]):  # returns a handle
@@ -141,14 +141,18 @@ class Server:
         free = self.budget - self.inflight_bytes
         left = self.max_slots
         for req in self.queue:
-            per = self.ex.slot_bytes(req)
-            cnt = min(req.B - req.next_colouring, left, free // per)
+            per = self.ex.slot_bytes(req, 1)
+            cnt = int(min(req.B - req.next_colouring, left, free // per))
+            # a slot's memory need not be exactly linear in its colourings: shrink until it fits
+            while cnt > 0 and self.ex.slot_bytes(req, cnt) > free:
+                cnt = cnt - max(1, cnt // 8)
             if cnt > 0:
-                slots.append(Slot(req, req.next_colouring, int(cnt), int(per * cnt)))
+                need = int(self.ex.slot_bytes(req, cnt))
+                slots.append(Slot(req, req.next_colouring, cnt, need))
                 req.next_colouring += int(cnt)
                 req.status = "running"
-                left -= int(cnt)
-                free -= per * cnt
+                left -= cnt
+                free -= need
             if req.next_colouring < req.B or left == 0:
                 break
         self.queue = deque(r for r in self.queue if r.next_colouring < r.B)
@@ -236,6 +240,18 @@ class Server:
         return self.completed
 
 
+class _Fixed:
+    """An already allocated workspace (the Workspace interface that count_packed uses)."""
+
+    def __init__(self, buf):
+        self.buf = buf
+
+    def get(self, nbytes, device):
+        if self.buf.numel() < nbytes:
+            raise ValueError("workspace too small")
+        return self.buf
+
+
 def latency_summary(reqs: list[Request]) -> dict:
     lat = np.array([r.latency for r in reqs if r.status == "done"])
     if len(lat) == 0:
@@ -249,8 +265,10 @@ def latency_summary(reqs: list[Request]) -> dict:
 # ------------------------------------------------------------------------------------------------
 
 class GpuExecutor(Executor):
-    """Runs batches through cc_batch_* (one launch per split level across the batch), each batch
-    on its own HIP stream; graphs stay resident in `graphs` (a list of Graph)."""
+    """Runs each slot of a batch as one packed count (cc_count_packed: the slot's colourings share
+    every table row and every pass over the graph), the batch's slots back to back on the batch's
+    HIP stream, batches on alternating streams; graphs stay resident in `graphs` (a list of
+    Graph)."""
 
     def __init__(self, graphs, device="cuda:0", seed_base: int = 0, n_streams: int = 2):
         import torch
@@ -261,6 +279,7 @@ class GpuExecutor(Executor):
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self._rr = 0
         self._plans: dict = {}
+        self._bytes: dict = {}
         self._Plan = Plan
         self.seed_base = seed_base
 
@@ -272,19 +291,25 @@ class GpuExecutor(Executor):
             self._plans[key] = p
         return p
 
-    def slot_bytes(self, req: Request) -> int:
-        """Device bytes of one colouring of `req`: the workspace a count of its plan on its graph
-        needs (table arena, chunk partials, root counts), plus its colours and result."""
-        from . import count_workspace_bytes
+    def slot_bytes(self, req: Request, count: int = 1) -> int:
+        """Device bytes of `count` colourings of `req` counted together: the packed-count
+        workspace of its plan on its graph (table arena, chunk partials, root counts, colour
+        transpose), plus the colours and results."""
+        from . import count_packed_workspace_bytes
         g = self.graphs[req.graph_id]
-        return count_workspace_bytes(self.plan(req), g) + g.n + 64
+        key = (req.tree_edges.tobytes(), req.graph_id, int(count))
+        b = self._bytes.get(key)
+        if b is None:
+            b = count_packed_workspace_bytes(self.plan(req), g, int(count)) + count * (g.n + 8) + 256
+            self._bytes[key] = b
+        return b
 
     def launch(self, slots: list[Slot]):
         import paper_1804_09764_amd as cc
         torch = self.torch
         st = self.streams[self._rr % len(self.streams)]
         self._rr += 1
-        keep, inst, outs = [], [], []
+        keep, outs = [], []
         # device buffers come from the allocator's default-stream pool and are marked as used on
         # the batch's stream, so memory freed by one batch can be reused by the next on any stream
         for s in slots:
@@ -292,27 +317,25 @@ class GpuExecutor(Executor):
             p = self.plan(s.req)
             C = torch.empty((s.count, g.n), dtype=torch.uint8, device=self.device)
             X = torch.empty(s.count, dtype=torch.float64, device=self.device)
-            C.record_stream(st)
-            X.record_stream(st)
+            ws = torch.empty(max(cc.count_packed_workspace_bytes(p, g, s.count), 256), dtype=torch.uint8,
+                             device=self.device)
+            for t in (C, X, ws):
+                t.record_stream(st)
             cc.colour(g, p.k, seed=self.seed_base + s.req.seed, first_iter=s.first, B=s.count, out=C, stream=st)
-            keep += [C, X]
+            cc.count_packed(p, g, C, workspace=_Fixed(ws), out=X, stream=st)
+            keep += [C, X, ws]
             outs.append(X)
-            for b in range(s.count):
-                inst.append((p, g, C[b], X[b:b + 1], None))
-        batch = cc.Batch(inst, levels=True)
-        ws = torch.empty(max(batch.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
-        ws.record_stream(st)
-        batch.run(ws, stream=st)
         ev = torch.cuda.Event()
         ev.record(st)
-        return {"event": ev, "batch": batch, "ws": ws, "keep": keep, "outs": outs, "stream": st}
+        return {"event": ev, "keep": keep, "outs": outs, "stream": st}
 
     def poll(self, handle) -> bool:
         return handle["event"].query()
 
     def collect(self, handle) -> list[np.ndarray]:
+        import paper_1804_09764_amd as cc
         handle["event"].synchronize()
-        handle["batch"].check(stream=handle["stream"])
+        cc.stream_check(handle["stream"])  # a device error on the batch's stream fails the batch
         return [x.cpu().numpy() for x in handle["outs"]]
 
     def estimate(self, req: Request, X: np.ndarray):

@@ -32,8 +32,8 @@ class SimExecutor(Executor):
         self.fail_rids = set(fail_rids)
         self.launched = []
 
-    def slot_bytes(self, req):
-        return self.bytes_per.get(req.rid, 100)
+    def slot_bytes(self, req, count=1):
+        return self.bytes_per.get(req.rid, 100) * count
 
     def launch(self, slots):
         n = sum(s.count for s in slots)
