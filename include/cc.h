@@ -299,6 +299,20 @@ cc_status cc_estimate(const cc_plan* plan, const double* X_host, int32_t B, doub
 cc_status cc_estimate_median_of_means(const cc_plan* plan, const double* X_host, int32_t B,
                                       int32_t groups, double* estimate);
 
+/*
+ * Host-side sample sizes for an (epsilon, delta)-approximation (Algorithm 1: the number of
+ * colourings, of order e^k log(1/delta) / epsilon^2, split into t groups of order log(1/delta)
+ * whose means are combined by a median). The paper gives only the orders; the constants are this
+ * library's reading: each group mean is within epsilon of the truth with probability >= 3/4 by
+ * Chebyshev when the group holds ceil(4 e^k / epsilon^2) colourings (the relative variance of one
+ * scaled colourful count taken as at most e^k), and the median of t = ceil(8 ln(1/delta)) such
+ * means fails only if half of them fail, which Hoeffding bounds by exp(-t/8) <= delta.
+ * *per_group = ceil(4 e^k / epsilon^2), *groups = max(1, ceil(8 ln(1/delta))); the total is their
+ * product. CC_ERANGE unless 1 <= k <= 16, 0 < epsilon < 1, 0 < delta < 1, or if per_group would
+ * exceed 2^62.
+ */
+cc_status cc_iterations(int32_t k, double epsilon, double delta, int64_t* per_group, int32_t* groups);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,7 +72,7 @@ class _Tuning(ctypes.Structure):
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
            "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
-           "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check",
+           "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
            "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read",
            "cc_batch_create", "cc_batch_workspace_bytes", "cc_batch_run", "cc_batch_check", "cc_batch_destroy"]
 
@@ -104,6 +104,8 @@ def lib() -> ctypes.CDLL:
         "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_stream_check": (ctypes.c_int, [P]),
+        "cc_iterations": (ctypes.c_int, [I32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(I64),
+                                         ctypes.POINTER(I32)]),
         "cc_estimate": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
         "cc_estimate_median_of_means": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ctypes.c_double)]),
@@ -357,6 +359,13 @@ def estimate(plan: Plan, X) -> tuple[float, float]:
     est, se = ctypes.c_double(), ctypes.c_double()
     _check(lib().cc_estimate(plan.handle, x.ctypes.data, len(x), ctypes.byref(est), ctypes.byref(se)))
     return est.value, se.value
+
+
+def iterations(k: int, epsilon: float, delta: float) -> tuple[int, int]:
+    """(colourings per group, groups) for an (epsilon, delta)-approximation (cc_iterations)."""
+    s, t = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().cc_iterations(k, epsilon, delta, ctypes.byref(s), ctypes.byref(t)))
+    return s.value, t.value
 
 
 def estimate_median_of_means(plan: Plan, X, groups: int) -> float:

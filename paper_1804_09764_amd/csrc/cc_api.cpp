@@ -922,4 +922,17 @@ cc_status cc_estimate_median_of_means(const cc_plan* P, const double* X_host, in
     return CC_OK;
 }
 
+cc_status cc_iterations(int32_t k, double epsilon, double delta, int64_t* per_group, int32_t* groups) {
+    if (!per_group || !groups) return fail(CC_EINVAL, "NULL argument");
+    if (k < 1 || k > CC_MAX_K) return fail(CC_ERANGE, "k must be in [1, 16]");
+    if (!(epsilon > 0.0 && epsilon < 1.0) || !(delta > 0.0 && delta < 1.0))
+        return fail(CC_ERANGE, "epsilon and delta must be in (0, 1)");
+    const long double s = ceill(4.0L * expl((long double)k) / ((long double)epsilon * (long double)epsilon));
+    if (s > 4.0e18L) return fail(CC_ERANGE, "per-group sample size too large");
+    const long double t = ceill(8.0L * logl(1.0L / (long double)delta));
+    *per_group = (int64_t)s;
+    *groups = t < 1.0L ? 1 : (int32_t)t;
+    return CC_OK;
+}
+
 }  // extern "C"

@@ -26,7 +26,6 @@
 
 #include "cc_internal.h"
 #include "cc_device.h"
-#include "cc_packed.h"
 
 namespace cc {
 
@@ -383,83 +382,6 @@ __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
     for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves)
         do_hub(S, t, N, Ash, lane);
-}
-
-// ---------------------------------------------------------------------------------------------
-// packed layout: one split for B colourings at once
-// ---------------------------------------------------------------------------------------------
-
-template <int J, bool P1>
-__global__ __launch_bounds__(256) void k_psplit(StepParams S) {
-    extern __shared__ double lds[];
-    const PMaps M = stage_maps(S, lds);
-    __syncthreads();
-    const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    double* N = lds + S.tab_doubles + (int64_t)wib * S.lds_wave;
-    double* Ash = N + S.a_off;
-    const int64_t n_tasks = S.n_chunks + S.n_ranges;
-    const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves)
-        do_ptask<J, P1>(S, t, N, Ash, M, lane);
-}
-
-__global__ __launch_bounds__(256) void k_phub(StepParams S) {
-    extern __shared__ double lds[];
-    const PMaps M = stage_maps(S, lds);
-    __syncthreads();
-    const int lane = lane_id();
-    const int wib = threadIdx.x / kWave;
-    double* N = lds + S.tab_doubles + (int64_t)wib * S.lds_wave;
-    double* Ash = N + S.a_off;
-    const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves)
-        do_phub(S, t, N, Ash, M, lane);
-}
-
-// [B][n] -> [n][B] bytes through 64 x 64 LDS tiles
-__global__ __launch_bounds__(256) void k_transpose_colours(const uint8_t* __restrict__ in, int64_t n, int B,
-                                                           uint8_t* __restrict__ out) {
-    __shared__ uint8_t tile[64][65];
-    const int64_t v0 = (int64_t)blockIdx.x * 64;
-    const int b0 = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += 4) {
-        const int b = b0 + r;
-        const int64_t v = v0 + tx;
-        tile[r][tx] = (b < B && v < n) ? in[(int64_t)b * n + v] : 0;
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t v = v0 + r;
-        const int b = b0 + tx;
-        if (b < B && v < n) out[v * B + b] = tile[tx][r];
-    }
-}
-
-// per-colouring sums of x[v][b]: block (range, 64 colourings), fixed order within and across blocks
-__global__ __launch_bounds__(256) void k_reduce_packed_blocks(const double* __restrict__ x, int64_t n, int B,
-                                                              int64_t per_block, double* __restrict__ partial) {
-    __shared__ double sh[256];
-    const int tb = threadIdx.x & 63, tv = threadIdx.x >> 6;
-    const int b = blockIdx.y * 64 + tb;
-    const int64_t lo = blockIdx.x * per_block;
-    const int64_t hi = lo + per_block < n ? lo + per_block : n;
-    double s = 0.0;
-    if (b < B)
-        for (int64_t v = lo + tv; v < hi; v += 4) s += x[v * B + b];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    if (tv == 0 && b < B) partial[(int64_t)blockIdx.x * B + b] = ((sh[tb] + sh[64 + tb]) + sh[128 + tb]) + sh[192 + tb];
-}
-
-__global__ __launch_bounds__(256) void k_reduce_packed_final(const double* __restrict__ partial, int blocks, int B,
-                                                             double* __restrict__ out) {
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= B) return;
-    double s = 0.0;
-    for (int i = 0; i < blocks; ++i) s += partial[(int64_t)i * B + b];
-    out[b] = s;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -861,116 +783,6 @@ hipError_t launch_reduce_batch(const ReduceDesc* rd_dev, int n_inst, int max_blo
     if (n_inst <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_batch_blocks, dim3((unsigned)max_blocks, (unsigned)n_inst), dim3(256), 0, st, rd_dev);
     hipLaunchKernelGGL(k_reduce_batch_final, dim3((unsigned)n_inst), dim3(256), 0, st, rd_dev);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------------------
-// packed layout launchers
-// ---------------------------------------------------------------------------------------------
-
-void packed_tile(StepParams* S) {
-    const int per = S->Cf + (S->a >= 2 ? S->Wa : 0);
-    const int width = S->p >= 2 ? S->Wp : S->k;
-    int cap = S->B < kWave ? S->B : kWave;
-    const int by_width = 256 / width > 1 ? 256 / width : 1;  // a tile row of about 2 KB
-    const int by_lds = 1024 / per > 1 ? 1024 / per : 1;      // about 8 KB of LDS per wavefront
-    if (cap > by_width) cap = by_width;
-    if (cap > by_lds) cap = by_lds;
-    if (cap < 1) cap = 1;
-    // equal tiles, a multiple of 4 colourings when that stays within the caps
-    const int tiles = (S->B + cap - 1) / cap;
-    int bt = (S->B + tiles - 1) / tiles;
-    if (((bt + 3) & ~3) <= cap) bt = (bt + 3) & ~3;
-    S->bt = bt;
-    int J = 1;
-    while (J < 8 && kWave * J < bt * width) J <<= 1;
-    S->pJ = J;
-    S->a_off = bt * S->Cf;
-    S->tg_off = S->a_off + (S->a >= 2 ? bt * S->Wa : 0);
-    S->cs_off = S->tg_off + (S->p >= 2 ? J * S->k * kWave / 4 : 0);
-    S->lds_wave = S->cs_off + (kWave * bt + 7) / 8;
-    S->tab_u16 = (S->a >= 2 ? 2 * S->npairs * S->Ws : 0) + (S->p >= 2 ? S->k * S->Wp : 0) + S->k * S->Nw;
-    S->tab_doubles = (S->tab_u16 + 3) / 4;
-}
-
-size_t packed_lds_bytes(const StepParams& S, int waves) {
-    return ((size_t)S.tab_doubles + (size_t)S.lds_wave * waves) * sizeof(double);
-}
-
-hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) {
-    packed_tile(&S);
-    if (packed_lds_bytes(S, 1) > 64 * 1024) return hipErrorInvalidConfiguration;
-    int w = 4;
-    while (w > 1 && packed_lds_bytes(S, w) > 64 * 1024) w >>= 1;
-    S.waves_per_block = w;
-    const int threads = w * kWave;
-    const size_t lds = packed_lds_bytes(S, w);
-    const int J = S.pJ;
-    const void* fn;
-    if (S.p == 1)
-        fn = J == 1 ? (const void*)k_psplit<1, true>
-           : J == 2 ? (const void*)k_psplit<2, true>
-           : J == 4 ? (const void*)k_psplit<4, true>
-                    : (const void*)k_psplit<8, true>;
-    else
-        fn = J == 1 ? (const void*)k_psplit<1, false>
-           : J == 2 ? (const void*)k_psplit<2, false>
-           : J == 4 ? (const void*)k_psplit<4, false>
-                    : (const void*)k_psplit<8, false>;
-    int per_cu = 0;
-    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
-    if (err != hipSuccess) return err;
-    if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const int64_t total = S.n_chunks + S.n_ranges;
-    int64_t blocks = (int64_t)per_cu * n_cu;
-    const int64_t need = (total + w - 1) / w;
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
-    if (total > 0) {
-        void* args[] = {&S};
-        err = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, lds, st);
-        if (err != hipSuccess) return err;
-        err = hipGetLastError();
-        if (err != hipSuccess) return err;
-    }
-    if (mid) {
-        err = hipEventRecord(mid, st);
-        if (err != hipSuccess) return err;
-    }
-    if (S.n_hubs > 0) {
-        int per_cu2 = 0;
-        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_phub, threads, lds);
-        if (err != hipSuccess) return err;
-        if (per_cu2 < 1) return hipErrorInvalidConfiguration;
-        int64_t b2 = (int64_t)per_cu2 * n_cu;
-        const int64_t need2 = (S.n_hubs + w - 1) / w;
-        if (b2 > need2) b2 = need2;
-        hipLaunchKernelGGL(k_phub, dim3((unsigned)b2), dim3(threads), lds, st, S);
-        err = hipGetLastError();
-    }
-    return err;
-}
-
-hipError_t launch_transpose_colours(const uint8_t* in, int64_t n, int B, uint8_t* out, hipStream_t st) {
-    if (n <= 0 || B <= 0) return hipSuccess;
-    const int64_t gx = (n + 63) / 64;
-    const int gy = (B + 63) / 64;
-    if (gx > 0x7FFFFFFF || gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_transpose_colours, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, in, n, B, out);
-    return hipGetLastError();
-}
-
-int packed_reduce_blocks(int64_t n) { return reduce_blocks_for(n); }
-
-hipError_t launch_reduce_packed(const double* x, int64_t n, int B, double* partial, double* out, hipStream_t st) {
-    if (B <= 0) return hipSuccess;
-    const int blocks = packed_reduce_blocks(n);
-    const int64_t per = (n + blocks - 1) / blocks;
-    const int gy = (B + 63) / 64;
-    if (gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_reduce_packed_blocks, dim3(blocks, gy), dim3(256), 0, st, x, n, B, per, partial);
-    hipLaunchKernelGGL(k_reduce_packed_final, dim3((B + 255) / 256), dim3(256), 0, st, (const double*)partial, blocks,
-                       B, out);
     return hipGetLastError();
 }
 

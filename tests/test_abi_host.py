@@ -131,6 +131,37 @@ def test_estimate_host():
         cc.estimate_median_of_means(p, [1.0, 2.0, 3.0], 2)
 
 
+def test_iterations_driver():
+    """Sample sizes of the (epsilon, delta) driver and their argument checks."""
+    for k, eps, delta in ((1, 0.5, 0.5), (3, 0.5, 0.1), (7, 0.2, 0.05), (12, 0.1, 0.01), (16, 0.9, 0.9)):
+        s, t = cc.iterations(k, eps, delta)
+        assert s == math.ceil(4 * math.exp(k) / eps ** 2)
+        assert t == max(1, math.ceil(8 * math.log(1 / delta)))
+    # monotone: tighter epsilon or delta, larger k -> more samples
+    assert cc.iterations(5, 0.1, 0.1)[0] > cc.iterations(5, 0.2, 0.1)[0]
+    assert cc.iterations(5, 0.1, 0.01)[1] > cc.iterations(5, 0.1, 0.1)[1]
+    assert cc.iterations(6, 0.1, 0.1)[0] > cc.iterations(5, 0.1, 0.1)[0]
+    for bad in ((0, 0.1, 0.1), (17, 0.1, 0.1), (5, 0.0, 0.1), (5, 1.0, 0.1), (5, 0.1, 0.0), (5, 0.1, 1.0)):
+        with pytest.raises(cc.CCError):
+            cc.iterations(*bad)
+
+
+def test_epsilon_delta_estimate_on_brute_force():
+    """Algorithm 1 end to end on the host: the driver's sample sizes, colourful counts of each
+    colouring (oracle), the median of group means; the result is within epsilon of the number of
+    copies counted by brute force (a statistical pin; seeds fixed)."""
+    rp, cl = inputs.er_graph(14, 30, 5)
+    for T in (inputs.path_tree(3), inputs.star_tree(4)):
+        k = len(T) + 1
+        copies = oracle.brute_count(rp, cl, None, T, root=0) / oracle.aut(T)
+        eps, delta = 0.5, 0.1
+        s, t = cc.iterations(k, eps, delta)
+        X = [oracle.count(rp, cl, oracle.colour(77, j, 14, k), T) for j in range(s * t)]
+        p = cc.Plan(T, bind=False)
+        est = cc.estimate_median_of_means(p, X, t)
+        assert abs(est - copies) <= eps * copies, (est, copies)
+
+
 def test_no_cpu_fallback_in_product():
     """The product package never imports the oracle."""
     pkg = os.path.join(ROOT, "paper_1804_09764_amd")
