@@ -158,6 +158,7 @@ cc::StepParams step_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     h.Nw = sp.Nw;
     h.npairs = sp.npairs;
     h.a_off = cc::split_a_off(sp.Nw);
+    h.stage_a = cc::split_stage_a(sp.Nw, sp.Wa, sp.a) ? 1 : 0;
     h.lds_wave = cc::split_lds_wave(sp.Nw, sp.Wa, sp.a);
     return h;
 }

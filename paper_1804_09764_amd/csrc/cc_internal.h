@@ -132,6 +132,7 @@ struct StepParams {
     int k, s, a, p, Wa, Wp, Ws, Nw, npairs;
     int lds_wave;       // doubles of LDS per wavefront
     int a_off;          // offset of the staged active row inside the wavefront's LDS slice
+    int stage_a;        // 1: the combine stages the active row in LDS; 0: reads it from HBM
     int stage_off;      // offset of the narrow-row stage inside the wavefront's LDS slice
     int waves_per_block;
     int cols_per_lane;  // 0 = choose from Wp
@@ -149,9 +150,12 @@ struct StepParams {
     const uint16_t* emap;     // E[cv][q]
 };
 
-// LDS layout of one split: N row (padded), then the active row when a >= 2
+// LDS layout of one split: N row (padded), then the active row when a >= 2 and both rows fit in
+// 16 KB per wavefront; wider active rows are read from HBM by the combine, which keeps the
+// wavefronts' LDS slices small enough for several to share a CU
+inline bool split_stage_a(int Nw, int Wa, int a) { return a >= 2 && pad_stride(Nw) + pad_stride(Wa) <= 2048; }
 inline int split_a_off(int Nw) { return pad_stride(Nw); }
-inline int split_lds_wave(int Nw, int Wa, int a) { return pad_stride(Nw) + (a >= 2 ? pad_stride(Wa) : 0); }
+inline int split_lds_wave(int Nw, int Wa, int a) { return pad_stride(Nw) + (split_stage_a(Nw, Wa, a) ? pad_stride(Wa) : 0); }
 
 // One segment of a batched launch: all work items of one phase of one split of one instance.
 // phase 0 = the split's tasks (chunks + light ranges), phase 1 = its cut-row finishes.

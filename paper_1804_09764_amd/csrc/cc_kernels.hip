@@ -258,24 +258,16 @@ __device__ void count_colours(const StepParams& S, int64_t beg, int64_t end, int
     if (lane < k - 1) N[lane] += (double)cnt;
 }
 
-// out row of v from N (LDS) and the active row of v
-__device__ void combine_store(const StepParams& S, int v, double* N, double* Ash, int lane) {
-    double* orow = S.O + (int64_t)v * S.ostride;
-    if (S.a == 1) {
-        // T' is the single vertex v: C(v, T', {col(v)}) = 1, so C(v, T, .) = N(v, .)
-        for (int r = lane; r < S.Ws; r += kWave) orow[r] = N[r];
-        return;
-    }
-    const double* arow = S.A + (int64_t)v * S.astride;
-    for (int r = lane; r < S.Wa; r += kWave) Ash[r] = arow[r];
-    wave_sync_lds();
+// output sets of v from N (LDS) and the active row A (staged in LDS, or in HBM when wide)
+__device__ __forceinline__ void combine_sets(const StepParams& S, double* orow, const double* A, const double* N,
+                                             int lane) {
     if (S.Ws >= kWave / 2) {
         for (int r = lane; r < S.Ws; r += kWave) {
             double sum = 0.0;
             const uint32_t* sp = S.split + r;
             for (int j = 0; j < S.npairs; ++j) {
                 const uint32_t pr = sp[(int64_t)j * S.Ws];
-                sum += Ash[pr & 0xFFFFu] * N[pr >> 16];
+                sum += A[pr & 0xFFFFu] * N[pr >> 16];
             }
             orow[r] = sum;
         }
@@ -291,11 +283,29 @@ __device__ void combine_store(const StepParams& S, int v, double* N, double* Ash
             const uint32_t* sp = S.split + r;
             for (int j = part; j < S.npairs; j += parts) {
                 const uint32_t pr = sp[(int64_t)j * S.Ws];
-                sum += Ash[pr & 0xFFFFu] * N[pr >> 16];
+                sum += A[pr & 0xFFFFu] * N[pr >> 16];
             }
         }
         for (int off = G; off < kWave; off <<= 1) sum += __shfl_xor(sum, off);
         if (part == 0 && r < S.Ws) orow[r] = sum;
+    }
+}
+
+// out row of v from N (LDS) and the active row of v
+__device__ void combine_store(const StepParams& S, int v, double* N, double* Ash, int lane) {
+    double* orow = S.O + (int64_t)v * S.ostride;
+    if (S.a == 1) {
+        // T' is the single vertex v: C(v, T', {col(v)}) = 1, so C(v, T, .) = N(v, .)
+        for (int r = lane; r < S.Ws; r += kWave) orow[r] = N[r];
+        return;
+    }
+    const double* arow = S.A + (int64_t)v * S.astride;
+    if (S.stage_a) {
+        for (int r = lane; r < S.Wa; r += kWave) Ash[r] = arow[r];
+        wave_sync_lds();
+        combine_sets(S, orow, Ash, N, lane);
+    } else {
+        combine_sets(S, orow, arow, N, lane);
     }
 }
 
@@ -634,17 +644,28 @@ int pick_J(int Wp, int want) {
     return 4;
 }
 
-// up to four wavefronts per workgroup, fewer when one wavefront's LDS slice is large
+// wavefronts per workgroup (4, 2 or 1; a workgroup stays within 64 KB of LDS): a smaller
+// workgroup only when it keeps over 10 % more wavefronts resident in a CU's 160 KB of LDS
 static int waves_for_lds(int lds_wave) {
-    int w = 4;
-    while (w > 1 && (size_t)lds_wave * w * sizeof(double) > 64 * 1024) w >>= 1;
-    return w;
+    const size_t per = (size_t)lds_wave * sizeof(double);
+    int best = 1;
+    size_t best_res = 0;
+    for (int w = 4; w >= 1; w >>= 1) {
+        if (per * w > 64 * 1024) continue;
+        const size_t res = (size_t)w * ((160 * 1024) / (per * w > 0 ? per * w : 1));
+        if (res * 10 > best_res * 11) {
+            best_res = res;
+            best = w;
+        }
+    }
+    return best;
 }
 
 hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) {
     // narrow passive rows take G lanes per row (a stage of 64 rows in LDS) unless a width is forced
     const int narrow = (S.p >= 2 && S.cols_per_lane == 0 && S.Wp <= 32) ? (S.Wp <= 16 ? 16 : 32) : 0;
     S.a_off = split_a_off(S.Nw);
+    S.stage_a = split_stage_a(S.Nw, S.Wa, S.a) ? 1 : 0;
     S.lds_wave = split_lds_wave(S.Nw, S.Wa, S.a);
     S.stage_off = S.lds_wave;
     S.lds_wave += narrow * kWave;

@@ -113,3 +113,41 @@ def test_rmat23_ef256_closed_forms_and_invariance(dev):
     torch.cuda.synchronize()
     a, b = float(Xa.cpu()[0]), float(Xb.cpu()[0])
     assert a > TWO53 and abs(a - b) <= 1e-12 * a
+
+
+def test_c2_batched_against_oracle(dev):
+    """R-MAT scale 18 (edge factor 16, seed 2), all 11 trees with 7 vertices x 64 colourings, counted
+    as bench.py's batched leg does (one packed count per tree, default tuning): sampled colourings
+    against the oracle."""
+    import torch
+    import paper_1804_09764_amd as cc
+    import oracle
+    rp_d, col_d = inputs.rmat_graph_gpu(18, 16, 2, device=dev)
+    G = cc.Graph(rp_d, col_d)
+    rp, col = rp_d.cpu().numpy(), col_d.cpu().numpy()
+    C = cc.colour(G, 7, seed=777, first_iter=0, B=64)
+    Ch = C.cpu().numpy()
+    for t, T in enumerate(inputs.all_trees(7)):
+        P = cc.Plan(T)
+        X = cc.count_packed(P, G, C)
+        torch.cuda.synchronize()
+        Xh = X.cpu().numpy()
+        for b in ((0, 63) if t < 3 else (t,)):
+            print(f"case: R-MAT 18 tree {t} colouring {b} against the oracle", flush=True)
+            _close(Xh[b], oracle.count(rp, col, Ch[b], T))
+
+
+def test_c3b_rmat20_u15_root_invariance(dev):
+    """R-MAT scale 20 / 15-vertex tree (seed 15): the total does not depend on the root."""
+    import torch
+    import paper_1804_09764_amd as cc
+    rp_d, col_d = inputs.rmat_graph_gpu(20, 16, 1, device=dev)
+    G = cc.Graph(rp_d, col_d)
+    T = inputs.pruefer_tree(15, 15)
+    c = cc.colour(G, 15, seed=777, first_iter=0, B=1)
+    print("case: R-MAT 20, 15-tree, planner root and root 0", flush=True)
+    Xa = cc.count(cc.Plan(T), G, c)
+    Xb = cc.count(cc.Plan(T, root=0), G, c)
+    torch.cuda.synchronize()
+    a, b = float(Xa.cpu()[0]), float(Xb.cpu()[0])
+    assert a > TWO53 and abs(a - b) <= 1e-12 * a
