@@ -191,6 +191,9 @@ hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_colour(uint64_t seed, uint64_t first_iter, int64_t n, int k, int B, uint8_t* out,
                          hipStream_t st);
+// root sums: blocks of kReducePerBlock values (at most 1024 blocks), then one final block; the
+// batched root sums use the same layout so that their totals equal a plain count's bit for bit
+constexpr int64_t kReducePerBlock = 8192;
 int reduce_blocks_for(int64_t n);
 hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* out, hipStream_t st);
 hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,

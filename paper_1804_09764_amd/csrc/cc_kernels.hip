@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_batch_level(const SegDesc* __restrict__
 __global__ __launch_bounds__(256) void k_reduce_batch_blocks(const ReduceDesc* rd) {
     __shared__ double sh[256];
     const ReduceDesc R = rd[blockIdx.y];
-    int64_t blocks = (R.n + 65535) / 65536;
+    int64_t blocks = (R.n + kReducePerBlock - 1) / kReducePerBlock;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     if ((int64_t)blockIdx.x >= blocks) return;
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch_blocks(const ReduceDesc* r
 __global__ __launch_bounds__(256) void k_reduce_batch_final(const ReduceDesc* rd) {
     __shared__ double sh[256];
     const ReduceDesc R = rd[blockIdx.x];
-    int64_t blocks = (R.n + 65535) / 65536;
+    int64_t blocks = (R.n + kReducePerBlock - 1) / kReducePerBlock;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     double s = 0.0;
@@ -615,7 +615,7 @@ hipError_t launch_colour(uint64_t seed, uint64_t first_iter, int64_t n, int k, i
 }
 
 int reduce_blocks_for(int64_t n) {
-    int64_t b = (n + 65535) / 65536;
+    int64_t b = (n + kReducePerBlock - 1) / kReducePerBlock;
     if (b < 1) b = 1;
     if (b > 1024) b = 1024;
     return (int)b;

@@ -181,7 +181,13 @@ hipError_t launch_transpose_colours(const uint8_t* in, int64_t n, int B, uint8_t
     return hipGetLastError();
 }
 
-int packed_reduce_blocks(int64_t n) { return reduce_blocks_for(n); }
+// one block per 1024 vertices (every block reads 1024 x B values), at most 1024 blocks
+int packed_reduce_blocks(int64_t n) {
+    int64_t b = (n + 1023) / 1024;
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
 
 hipError_t launch_reduce_packed(const double* x, int64_t n, int B, double* partial, double* out, hipStream_t st) {
     if (B <= 0) return hipSuccess;
