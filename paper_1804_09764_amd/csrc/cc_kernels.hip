@@ -303,10 +303,9 @@ __device__ void combine_store(const StepParams& S, int v, double* N, double* Ash
     if (S.stage_a) {
         for (int r = lane; r < S.Wa; r += kWave) Ash[r] = arow[r];
         wave_sync_lds();
-        combine_sets(S, orow, Ash, N, lane);
-    } else {
-        combine_sets(S, orow, arow, N, lane);
     }
+    // one copy of the loop for both cases (a second inlined copy costs registers in every variant)
+    combine_sets(S, orow, S.stage_a ? (const double*)Ash : arow, N, lane);
 }
 
 // one light row: neighbour sum into LDS, then combine and store
@@ -370,8 +369,10 @@ __device__ __forceinline__ void do_hub(const StepParams& S, int64_t t, double* N
 
 // Tasks (chunks of cut rows first, then ranges of light rows, all of about `chunk` entries) are
 // dealt to the persistent wavefronts round-robin: no shared counter, one fixed owner per task.
+// The second bound is the minimum wavefronts per SIMD the register allocation must allow: the
+// 16-lane narrow variant would otherwise sit just above the 128-register step to four.
 template <int J, int NARROW>
-__global__ __launch_bounds__(256) void k_split(StepParams S) {
+__global__ __launch_bounds__(256, (NARROW == 16 ? 4 : 1)) void k_split(StepParams S) {
     extern __shared__ double lds[];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(512) void k_batch_inst(const SegDesc* __restrict__ 
 // level-ordered segment list, which lie in segments [seg_lo, seg_hi), are dealt round-robin to
 // persistent wavefronts; every item of a level is independent.
 template <int J, int NARROW>
-__global__ __launch_bounds__(256) void k_batch_level(const SegDesc* __restrict__ segs, int seg_lo, int seg_hi,
+__global__ __launch_bounds__(256, (NARROW == 16 ? 4 : 1)) void k_batch_level(const SegDesc* __restrict__ segs, int seg_lo, int seg_hi,
                                                      int64_t item_lo, int64_t item_hi, int lds_wave, int wpb) {
     extern __shared__ double lds[];
     const int lane = lane_id();

@@ -93,7 +93,9 @@ void packed_tile(StepParams* S) {
     const int per = S->Cf + (S->a >= 2 ? S->Wa : 0);
     const int width = S->p >= 2 ? S->Wp : S->k;
     int cap = S->B < kWave ? S->B : kWave;
-    const int by_width = 256 / width > 1 ? 256 / width : 1;  // a tile row of about 2 KB
+    // tile elements per lane: up to 4 (p >= 2: a tile row of about 2 KB) or 8 (p = 1: counts in registers)
+    const int elems = S->p >= 2 ? 256 : 512;
+    const int by_width = elems / width > 1 ? elems / width : 1;
     const int by_lds = 1024 / per > 1 ? 1024 / per : 1;      // about 8 KB of LDS per wavefront
     if (cap > by_width) cap = by_width;
     if (cap > by_lds) cap = by_lds;
