@@ -209,6 +209,41 @@ cc_status cc_count_packed_workspace_bytes(const cc_plan* plan, const cc_graph* g
 cc_status cc_count_packed(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
                           void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
 
+/* ------------------------------------------------------------------------------------------ */
+/* Packed count of several templates of one size, sharing equal sub-template tables            */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct cc_multi cc_multi;
+
+/*
+ * Prepare a count of n_plans templates with the same k over the same colourings (host only; the
+ * plans must outlive the object). Eq. 1 gives every rooted sub-template T_i of a partition the
+ * same table C(., T_i, .) whichever template and partition it comes from (Section 2.1), so the
+ * table of each distinct rooted sub-template (equal canonical forms) is computed once, in the
+ * first template that needs it, and kept until its last use; a template's splits whose output is
+ * already there are not run, nor the splits that only feed them. CC_EINVAL for NULL plans or
+ * different k.
+ */
+cc_status cc_multi_create(int32_t n_plans, const cc_plan* const* plans, cc_multi** out);
+
+/* Splits that run (n_steps), splits of all plans before sharing (n_splits), shared tables. */
+cc_status cc_multi_info_get(const cc_multi* multi, int32_t* n_steps, int64_t* n_splits, int32_t* n_tables);
+
+void cc_multi_destroy(cc_multi* multi);
+
+/* Device workspace needed by cc_count_packed_multi for this multi-template count, graph and B. */
+cc_status cc_count_packed_multi_workspace_bytes(const cc_multi* multi, const cc_graph* g, int32_t B, size_t* bytes);
+
+/*
+ * X_dev[p*B + b] = the colourful count of template p under colouring b (colours_dev as for
+ * cc_count_packed: B*n bytes, colouring b at colours_dev + b*n), every template's tables in the
+ * packed layout. Exact below 2^53; above, within the rounding of a fixed summation order (a shared
+ * table may come from another partition than the template's own, so values above 2^53 can differ
+ * in the last bits from cc_count_packed of that template alone). Errors as cc_count_packed.
+ */
+cc_status cc_count_packed_multi(const cc_multi* multi, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
+                                void* ws_dev, size_t ws_bytes, double* X_dev, void* stream);
+
 /* Synchronise `stream` and report any device error of the work queued on it (CC_EDEVICE). */
 cc_status cc_stream_check(void* stream);
 

@@ -73,6 +73,8 @@ EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split
            "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
+           "cc_multi_create", "cc_multi_info_get", "cc_multi_destroy", "cc_count_packed_multi_workspace_bytes",
+           "cc_count_packed_multi",
            "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read",
            "cc_batch_create", "cc_batch_workspace_bytes", "cc_batch_run", "cc_batch_check", "cc_batch_destroy"]
 
@@ -104,6 +106,11 @@ def lib() -> ctypes.CDLL:
         "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_stream_check": (ctypes.c_int, [P]),
+        "cc_multi_create": (ctypes.c_int, [I32, P, ctypes.POINTER(P)]),
+        "cc_multi_info_get": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32)]),
+        "cc_multi_destroy": (None, [P]),
+        "cc_count_packed_multi_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
+        "cc_count_packed_multi": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P]),
         "cc_iterations": (ctypes.c_int, [I32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(I64),
                                          ctypes.POINTER(I32)]),
         "cc_estimate": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double),
@@ -351,6 +358,58 @@ def count_packed(plan: Plan, graph: Graph, colours, per_vertex: bool = False, wo
 def stream_check(stream=None):
     """Synchronise `stream` (default: the current one) and raise CCError on a device error."""
     _check(lib().cc_stream_check(_stream(stream)))
+
+
+class Multi:
+    """Several templates of one size counted together over the same colourings, sharing the
+    tables of equal rooted sub-templates (cc_multi_*)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().cc_multi_create(len(self.plans), arr, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def info(self) -> dict:
+        st, ns, nt = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().cc_multi_info_get(self._h, ctypes.byref(st), ctypes.byref(ns), ctypes.byref(nt)))
+        return {"steps": st.value, "splits": ns.value, "tables": nt.value}
+
+    def workspace_bytes(self, graph: "Graph", B: int) -> int:
+        nb = ctypes.c_size_t()
+        _check(lib().cc_count_packed_multi_workspace_bytes(self._h, graph.handle, B, ctypes.byref(nb)))
+        return nb.value
+
+    def count(self, graph: "Graph", colours, workspace: Workspace | None = None, out=None, stream=None):
+        """X[p, b] for every template p and colouring b of `colours` ([B, n] uint8 on the GPU)."""
+        import torch
+        if colours.dim() == 1:
+            colours = colours.view(1, -1)
+        B = colours.shape[0]
+        if colours.shape[1] != graph.n:
+            raise ValueError("colours must be [B, n]")
+        dev = graph.row_ptr.device
+        ws = (workspace or Workspace()).get(self.workspace_bytes(graph, B), dev)
+        X = out if out is not None else torch.empty((len(self.plans), B), dtype=torch.float64, device=dev)
+        _check(lib().cc_count_packed_multi(self._h, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B,
+                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                           _dev_ptr(X, torch.float64, "X"), _stream(stream)))
+        return X
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().cc_multi_destroy(h)
+            except Exception:
+                pass
+            self._h = None
 
 
 def estimate(plan: Plan, X) -> tuple[float, float]:

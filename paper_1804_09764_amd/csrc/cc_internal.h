@@ -43,6 +43,7 @@ struct Split {
 struct Table {
     int size;        // sub-template size t
     int W;           // C(k-1, t-1)
+    std::string key; // canonical form of the rooted sub-template (equal keys: equal tables)
     int stride;      // row stride in doubles
     int64_t col_off; // offset in columns (1 column = n_pad doubles) inside the table arena
 };
@@ -236,6 +237,21 @@ struct cc_graph {
     int32_t cols_per_lane = 0;
     int device = 0;
     int n_cu = 0;
+};
+
+// Several templates of one size counted together with packed rows; tables of equal rooted
+// sub-templates (equal canonical keys) are computed once and shared.
+struct cc_multi {
+    int k = 0;
+    std::vector<const cc_plan*> plans;
+    struct Step {
+        int plan, split;       // the split that runs (plan index, split index in that plan)
+        int act, pas, out;     // global table ids (-1: a single vertex; out -2: the plan's root counts)
+        std::vector<int> release;  // global tables whose last use is this step
+    };
+    std::vector<Step> steps;
+    std::vector<int> table_W;  // per global table: entries per colouring
+    int64_t n_splits = 0;      // splits of all plans together (before sharing)
 };
 
 struct cc_batch {

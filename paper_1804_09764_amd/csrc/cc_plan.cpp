@@ -255,15 +255,27 @@ struct Schedule {
     int64_t live_peak = 0;
 };
 
+// AHU canonical string of the rooted subtree of x in R
+std::string rcanon(const Rooted& R, int x) {
+    std::vector<std::string> ch;
+    for (int y : R.kids[x]) ch.push_back(rcanon(R, y));
+    std::sort(ch.begin(), ch.end());
+    std::string s = "(";
+    for (auto& c : ch) s += c;
+    return s + ")";
+}
+
 Schedule schedule(int k, const Rooted& R, int root) {
     Schedule S;
     Arena A;
     int64_t live = 0;
     std::function<int(int)> compute = [&](int x) -> int {
         int act = -1, a = 1;
+        std::vector<std::string> attached;  // canonical forms of the children attached so far
         for (size_t j = 0; j < R.kids[x].size(); ++j) {
             int c = R.kids[x][j];
             int pas = compute(c);
+            attached.push_back(rcanon(R, c));
             int p = R.size[c];
             int s = a + p;
             bool last_root = (x == root) && (j + 1 == R.kids[x].size());
@@ -277,6 +289,11 @@ Schedule schedule(int k, const Rooted& R, int root) {
             } else {
                 Table t{};
                 t.size = s; t.W = sp.Ws; t.stride = pad_stride(t.W);
+                std::vector<std::string> sorted_kids = attached;
+                std::sort(sorted_kids.begin(), sorted_kids.end());
+                t.key = "(";
+                for (auto& ck : sorted_kids) t.key += ck;
+                t.key += ")";
                 t.col_off = A.alloc(t.stride);
                 live += t.stride;
                 S.tables.push_back(t);

@@ -162,6 +162,25 @@ def test_epsilon_delta_estimate_on_brute_force():
         assert abs(est - copies) <= eps * copies, (est, copies)
 
 
+def test_multi_template_sharing_counts():
+    """Equal rooted sub-templates are computed once: fewer splits run than the templates hold, and
+    one template alone never runs more splits than it has."""
+    for k in (5, 7, 8):
+        plans = [cc.Plan(T, bind=False) for T in inputs.all_trees(k)]
+        info = cc.Multi(plans).info
+        assert info["splits"] == sum(len(p.splits) for p in plans)
+        assert info["steps"] < info["splits"]
+        for p in plans:
+            one = cc.Multi([p]).info
+            assert one["steps"] <= len(p.splits)
+    # a spider with three equal legs: the leg's tables are computed once
+    legs = [(0, 1), (1, 2), (0, 3), (3, 4), (0, 5), (5, 6)]
+    p = cc.Plan(np.array(legs, dtype=np.int32), root=0, bind=False)
+    assert cc.Multi([p]).info["steps"] < len(p.splits)
+    with pytest.raises(cc.CCError):
+        cc.Multi([cc.Plan(inputs.path_tree(4), bind=False), cc.Plan(inputs.path_tree(5), bind=False)])
+
+
 def test_no_cpu_fallback_in_product():
     """The product package never imports the oracle."""
     pkg = os.path.join(ROOT, "paper_1804_09764_amd")

@@ -196,3 +196,51 @@ def test_packed_empty_and_degenerate(dev):
         assert X.cpu().tolist() == ([10.0] * 3 if k == 1 else [0.0] * 3)
     with pytest.raises(cc.CCError):
         cc.count_packed(cc.Plan(inputs.path_tree(3)), G, torch.zeros((0, 10), dtype=torch.uint8, device="cuda"))
+
+
+def test_multi_template_count_shares_tables_and_matches(dev):
+    """All 11 trees with 7 vertices counted together (shared sub-template tables) equal each
+    template's own packed count and the oracle."""
+    import torch
+    cc = _cc()
+    rp, cl = inputs.rmat_graph(10, 16, 4)
+    n = len(rp) - 1
+    G = cc.Graph.from_numpy(rp, cl, hub_threshold=64, chunk=64)
+    trees = inputs.all_trees(7)
+    plans = [cc.Plan(T) for T in trees]
+    M = cc.Multi(plans)
+    assert M.info["steps"] < M.info["splits"]
+    cols = oracle_colourings(n, 7, 5, 3)
+    C = torch.from_numpy(cols).cuda()
+    X = M.count(G, C)
+    single = [cc.count_packed(P, G, C) for P in plans]
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    for t, T in enumerate(trees):
+        print(f"case: multi-template count, tree {t}", flush=True)
+        assert_parity(Xh[t], single[t].cpu().numpy())
+        assert_parity([Xh[t, 0], Xh[t, 4]], [oracle.count(rp, cl, cols[0], T), oracle.count(rp, cl, cols[4], T)])
+
+
+def test_multi_template_duplicates_roots_and_errors(dev):
+    import torch
+    cc = _cc()
+    rp, cl = inputs.er_graph(300, 1500, 6)
+    G = cc.Graph.from_numpy(rp, cl)
+    T = inputs.pruefer_tree(8, 4)
+    plans = [cc.Plan(T), cc.Plan(T, root=0), cc.Plan(T), cc.Plan(inputs.path_tree(8))]
+    M = cc.Multi(plans)
+    C = cc.colour(G, 8, seed=3, first_iter=0, B=3)
+    X = M.count(G, C)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    assert np.array_equal(Xh[0], Xh[2])
+    assert_parity(Xh[1], Xh[0])
+    for b in range(3):
+        assert_parity([Xh[0, b], Xh[3, b]], [oracle.count(rp, cl, C[b].cpu().numpy(), T),
+                                             oracle.count(rp, cl, C[b].cpu().numpy(), inputs.path_tree(8))])
+    one = cc.Multi([cc.Plan(np.zeros((0, 2), np.int32))]).count(G, cc.colour(G, 1, 1, 0, 2))
+    torch.cuda.synchronize()
+    assert one.cpu().tolist() == [[300.0, 300.0]]
+    with pytest.raises(cc.CCError):
+        cc.Multi([cc.Plan(inputs.path_tree(4)), cc.Plan(inputs.path_tree(5))])
