@@ -229,6 +229,10 @@ cc_status cc_multi_create(int32_t n_plans, const cc_plan* const* plans, cc_multi
 /* Splits that run (n_steps), splits of all plans before sharing (n_splits), shared tables. */
 cc_status cc_multi_info_get(const cc_multi* multi, int32_t* n_steps, int64_t* n_splits, int32_t* n_tables);
 
+/* Step i (0 <= i < n_steps, execution order): the plan index and that plan's split index it runs
+ * (cc_plan_split_get gives the split's sizes). CC_ERANGE for i out of range. */
+cc_status cc_multi_step_get(const cc_multi* multi, int32_t i, int32_t* plan, int32_t* split);
+
 void cc_multi_destroy(cc_multi* multi);
 
 /* Device workspace needed by cc_count_packed_multi for this multi-template count, graph and B. */

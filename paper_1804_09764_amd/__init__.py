@@ -73,7 +73,8 @@ EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split
            "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
-           "cc_multi_create", "cc_multi_info_get", "cc_multi_destroy", "cc_count_packed_multi_workspace_bytes",
+           "cc_multi_create", "cc_multi_info_get", "cc_multi_step_get", "cc_multi_destroy",
+           "cc_count_packed_multi_workspace_bytes",
            "cc_count_packed_multi",
            "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read",
            "cc_batch_create", "cc_batch_workspace_bytes", "cc_batch_run", "cc_batch_check", "cc_batch_destroy"]
@@ -108,6 +109,7 @@ def lib() -> ctypes.CDLL:
         "cc_stream_check": (ctypes.c_int, [P]),
         "cc_multi_create": (ctypes.c_int, [I32, P, ctypes.POINTER(P)]),
         "cc_multi_info_get": (ctypes.c_int, [P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32)]),
+        "cc_multi_step_get": (ctypes.c_int, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "cc_multi_destroy": (None, [P]),
         "cc_count_packed_multi_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed_multi": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P]),
@@ -380,6 +382,16 @@ class Multi:
         st, ns, nt = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
         _check(lib().cc_multi_info_get(self._h, ctypes.byref(st), ctypes.byref(ns), ctypes.byref(nt)))
         return {"steps": st.value, "splits": ns.value, "tables": nt.value}
+
+    @property
+    def steps(self) -> list[tuple[int, int]]:
+        """(plan index, split index) of every split that runs, in execution order."""
+        out = []
+        for i in range(self.info["steps"]):
+            p, j = ctypes.c_int32(), ctypes.c_int32()
+            _check(lib().cc_multi_step_get(self._h, i, ctypes.byref(p), ctypes.byref(j)))
+            out.append((p.value, j.value))
+        return out
 
     def workspace_bytes(self, graph: "Graph", B: int) -> int:
         nb = ctypes.c_size_t()

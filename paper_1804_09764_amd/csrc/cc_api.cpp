@@ -781,6 +781,14 @@ cc_status cc_multi_info_get(const cc_multi* M, int32_t* n_steps, int64_t* n_spli
     return CC_OK;
 }
 
+cc_status cc_multi_step_get(const cc_multi* M, int32_t i, int32_t* plan, int32_t* split) {
+    if (!M || !plan || !split) return fail(CC_EINVAL, "NULL argument");
+    if (i < 0 || (size_t)i >= M->steps.size()) return fail(CC_ERANGE, "step index out of range");
+    *plan = M->steps[(size_t)i].plan;
+    *split = M->steps[(size_t)i].split;
+    return CC_OK;
+}
+
 void cc_multi_destroy(cc_multi* M) { delete M; }
 
 cc_status cc_count_packed_multi_workspace_bytes(const cc_multi* M, const cc_graph* G, int32_t B, size_t* bytes) {

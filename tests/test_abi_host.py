@@ -173,6 +173,14 @@ def test_multi_template_sharing_counts():
         for p in plans:
             one = cc.Multi([p]).info
             assert one["steps"] <= len(p.splits)
+    # every template's root split runs, each exactly once, and steps refer to real splits
+    plans = [cc.Plan(T, bind=False) for T in inputs.all_trees(7)]
+    m = cc.Multi(plans)
+    steps = m.steps
+    assert len(steps) == m.info["steps"] and len(set(steps)) == len(steps)
+    for p_i, p in enumerate(plans):
+        assert (p_i, len(p.splits) - 1) in steps
+    assert all(0 <= j < len(plans[p_i].splits) for p_i, j in steps)
     # a spider with three equal legs: the leg's tables are computed once
     legs = [(0, 1), (1, 2), (0, 3), (3, 4), (0, 5), (5, 6)]
     p = cc.Plan(np.array(legs, dtype=np.int32), root=0, bind=False)
