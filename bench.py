@@ -273,6 +273,7 @@ def bench(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": f"{'k_psplit' if dom_packed else 'k_split'} split {dom} (s={s}, a={a}, p={p})",
                      "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg,
