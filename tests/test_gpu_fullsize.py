@@ -117,8 +117,8 @@ def test_rmat23_ef256_closed_forms_and_invariance(dev):
 
 def test_c2_batched_against_oracle(dev):
     """R-MAT scale 18 (edge factor 16, seed 2), all 11 trees with 7 vertices x 64 colourings, counted
-    as bench.py's batched leg does (one packed count per tree, default tuning): sampled colourings
-    against the oracle."""
+    as bench.py's batched leg does (one multi-template packed count, default tuning) and as one
+    packed count per tree: sampled colourings against the oracle."""
     import torch
     import paper_1804_09764_amd as cc
     import oracle
@@ -127,14 +127,20 @@ def test_c2_batched_against_oracle(dev):
     rp, col = rp_d.cpu().numpy(), col_d.cpu().numpy()
     C = cc.colour(G, 7, seed=777, first_iter=0, B=64)
     Ch = C.cpu().numpy()
-    for t, T in enumerate(inputs.all_trees(7)):
-        P = cc.Plan(T)
+    trees = inputs.all_trees(7)
+    plans = [cc.Plan(T) for T in trees]
+    Xm = cc.Multi(plans).count(G, C)
+    torch.cuda.synchronize()
+    Xm = Xm.cpu().numpy()
+    for t, (T, P) in enumerate(zip(trees, plans)):
         X = cc.count_packed(P, G, C)
         torch.cuda.synchronize()
         Xh = X.cpu().numpy()
         for b in ((0, 63) if t < 3 else (t,)):
             print(f"case: R-MAT 18 tree {t} colouring {b} against the oracle", flush=True)
-            _close(Xh[b], oracle.count(rp, col, Ch[b], T))
+            want = oracle.count(rp, col, Ch[b], T)
+            _close(Xm[t, b], want)
+            _close(Xh[b], want)
 
 
 def test_c3b_rmat20_u15_root_invariance(dev):
