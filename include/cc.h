@@ -70,6 +70,11 @@ typedef struct cc_plan cc_plan;
 /* flags for cc_plan_create */
 #define CC_PLAN_CENTRE_SMALLEST 1u  /* root = centre, attach children smallest subtree first
                                        (the fixed reference partition used for bookkeeping) */
+#define CC_PLAN_NO_SHARING 2u       /* run every split of the partition. By default a split whose
+                                       rooted sub-template equals one computed earlier in the same
+                                       template (equal canonical forms: the same table, Eq. 1) is
+                                       not run, and its consumers read the earlier table; the
+                                       reference partition never shares */
 
 /*
  * k in [1, CC_MAX_K]; edges (host) = 2*(k-1) int32 vertex ids in [0, k) forming a tree.

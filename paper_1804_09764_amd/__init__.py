@@ -25,6 +25,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcc.so")
 
 CC_PLAN_CENTRE_SMALLEST = 1
+CC_PLAN_NO_SHARING = 2
 CC_GRAPH_TRUST = 1
 
 _STATUS = {0: "CC_OK", -1: "CC_EINVAL", -2: "CC_ERANGE", -3: "CC_ENOMEM", -4: "CC_ENOSPC",

@@ -313,18 +313,77 @@ Schedule schedule(int k, const Rooted& R, int root) {
     return S;
 }
 
+// The splits of S that must run when equal rooted sub-templates (equal table keys) are computed
+// once: walking from the root split, a table whose key was produced before is reused, and the
+// splits that would only feed it are dropped. Tables are renumbered, and the arena is first-fit
+// again over the shorter sequence with each table released after its last use.
+Schedule share_tables(const Schedule& S) {
+    Schedule D;
+    if (S.splits.empty()) return D;
+    std::vector<int> producer(S.tables.size(), -1);
+    for (size_t j = 0; j < S.splits.size(); ++j)
+        if (S.splits[j].out >= 0) producer[(size_t)S.splits[j].out] = (int)j;
+    std::map<std::string, int> have;
+    std::function<int(int)> need = [&](int t) -> int {
+        auto it = have.find(S.tables[(size_t)t].key);
+        if (it != have.end()) return it->second;
+        Split sp = S.splits[(size_t)producer[(size_t)t]];
+        sp.act = sp.act >= 0 ? need(sp.act) : -1;
+        sp.pas = sp.pas >= 0 ? need(sp.pas) : -1;
+        D.tables.push_back(S.tables[(size_t)t]);
+        sp.out = (int)D.tables.size() - 1;
+        have[S.tables[(size_t)t].key] = sp.out;
+        D.splits.push_back(sp);
+        return sp.out;
+    };
+    Split root = S.splits.back();
+    root.act = root.act >= 0 ? need(root.act) : -1;
+    root.pas = root.pas >= 0 ? need(root.pas) : -1;
+    D.splits.push_back(root);
+    // liveness over the new sequence
+    std::vector<int> last(D.tables.size(), -1);
+    for (size_t j = 0; j < D.splits.size(); ++j) {
+        if (D.splits[j].act >= 0) last[(size_t)D.splits[j].act] = (int)j;
+        if (D.splits[j].pas >= 0) last[(size_t)D.splits[j].pas] = (int)j;
+    }
+    Arena A;
+    int64_t live = 0;
+    for (size_t j = 0; j < D.splits.size(); ++j) {
+        const Split& sp = D.splits[j];
+        if (sp.out >= 0) {
+            Table& t = D.tables[(size_t)sp.out];
+            t.col_off = A.alloc(t.stride);
+            live += t.stride;
+        }
+        D.live_peak = std::max(D.live_peak, live);
+        for (int in : {sp.act, sp.pas == sp.act ? -1 : sp.pas})  // each input once
+            if (in >= 0 && last[(size_t)in] == (int)j) {
+                A.release(D.tables[(size_t)in].col_off);
+                live -= D.tables[(size_t)in].stride;
+            }
+    }
+    D.arena_cols = A.peak;
+    return D;
+}
+
 }  // namespace
 
 int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off) {
-    // the allocation order of schedule(): each split allocates its output table, then releases
-    // its active and passive inputs
+    // the plan's allocation order: each split allocates its output table, then releases the
+    // inputs it is the last reader of (a shared table has several readers)
+    std::vector<int> last(P->tables.size(), -1);
+    for (size_t j = 0; j < P->splits.size(); ++j) {
+        if (P->splits[j].act >= 0) last[(size_t)P->splits[j].act] = (int)j;
+        if (P->splits[j].pas >= 0) last[(size_t)P->splits[j].pas] = (int)j;
+    }
     Arena A;
     col_off->assign(P->tables.size(), 0);
-    for (const Split& sp : P->splits) {
+    for (size_t j = 0; j < P->splits.size(); ++j) {
+        const Split& sp = P->splits[j];
         if (sp.out >= 0)
             (*col_off)[(size_t)sp.out] = A.alloc(packed_cols(P->tables[(size_t)sp.out].W, B));
-        if (sp.act >= 0) A.release((*col_off)[(size_t)sp.act]);
-        if (sp.pas >= 0) A.release((*col_off)[(size_t)sp.pas]);
+        for (int in : {sp.act, sp.pas == sp.act ? -1 : sp.pas})  // each input once
+            if (in >= 0 && last[(size_t)in] == (int)j) A.release((*col_off)[(size_t)in]);
     }
     return A.peak;
 }
@@ -368,14 +427,16 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
     // choose the root: fewest doubles gathered per edge (weighted 256x: one gathered double per
     // edge costs about as much HBM time as 256 combine multiply-adds per vertex at average degree
     // ~30), then the smaller table arena
+    const bool share = !reference && (flags & CC_PLAN_NO_SHARING) == 0;
     double best_cost = 1e300;
-    Schedule best;
+    Schedule best, best_full;
     Rooted bestR;
     int best_root = candidates[0];
     for (int r : candidates) {
         Rooted R = root_at(t, r);
         order_children(k, &R, reference);
-        Schedule S = schedule(k, R, r);
+        const Schedule full = schedule(k, R, r);
+        const Schedule S = share ? share_tables(full) : full;
         int64_t g = 0, c = 0;
         for (auto& sp : S.splits) {
             if (sp.p >= 2) g += sp.Wp;
@@ -385,6 +446,7 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
         if (cost < best_cost) {
             best_cost = cost;
             best = S;
+            best_full = full;
             bestR = R;
             best_root = r;
         }
@@ -395,14 +457,15 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
     P->arena_cols = best.arena_cols;
     P->peak_live_cols = best.live_peak;
 
-    // bookkeeping
+    // bookkeeping (Table 3 counts every split of the partition, shared or not)
     P->t3_memory = P->t3_compute = P->gather_per_edge = P->combine_per_vertex = 0;
     P->max_Nw = 0;
-    for (auto& sp : P->splits) {
+    for (auto& sp : best_full.splits)
         if (sp.out != -2) {
             P->t3_memory += binom(k, sp.s);
             P->t3_compute += binom(k, sp.s) * binom(sp.s, sp.a);
         }
+    for (auto& sp : P->splits) {
         if (sp.p >= 2) P->gather_per_edge += sp.Wp;
         if (sp.a >= 2) P->combine_per_vertex += (int64_t)sp.Ws * sp.npairs;
         P->max_Nw = std::max(P->max_Nw, sp.Nw);

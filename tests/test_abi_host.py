@@ -67,13 +67,34 @@ def test_partition_invariants(k):
     for seed in range(5):
         T = inputs.pruefer_tree(k, seed)
         for root in (-1, 0, k - 1):
-            p = cc.Plan(T, root=root, bind=False)
+            p = cc.Plan(T, root=root, bind=False, flags=cc.CC_PLAN_NO_SHARING)
             assert p.info.n_splits == k - 1
             assert p.splits[-1][0] == k
             for s, a, pp in p.splits:
                 assert s == a + pp and a >= 1 and pp >= 1
             # the passive sizes are the subtree sizes of the non-root vertices
             assert sorted(pp for _, _, pp in p.splits) == sorted(_subtree_sizes(T, p.info.root))
+
+
+@pytest.mark.parametrize("k", range(2, 17))
+def test_shared_splits_are_a_subset(k):
+    """With sharing (the default), the splits that run are a sub-multiset of the partition's, the
+    root split is last, and the table arena is no larger; the reference partition never shares."""
+    from collections import Counter
+    for seed in range(5):
+        T = inputs.pruefer_tree(k, seed)
+        for root in (0, k - 1):
+            full = cc.Plan(T, root=root, bind=False, flags=cc.CC_PLAN_NO_SHARING)
+            p = cc.Plan(T, root=root, bind=False)
+            assert p.splits[-1] == full.splits[-1]
+            assert not (Counter(p.splits) - Counter(full.splits))
+            assert p.info.table3_memory == full.info.table3_memory
+        ref = cc.Plan(T, bind=False, flags=cc.CC_PLAN_CENTRE_SMALLEST)
+        assert ref.info.n_splits == k - 1
+    # two equal branches below the root: the branch's splits run once
+    legs = [(0, 1), (1, 2), (0, 3), (3, 4), (0, 5), (5, 6)]
+    p = cc.Plan(np.array(legs, dtype=np.int32), root=0, bind=False)
+    assert p.info.n_splits < 6
 
 
 def _subtree_sizes(T, root):
@@ -181,9 +202,10 @@ def test_multi_template_sharing_counts():
     for p_i, p in enumerate(plans):
         assert (p_i, len(p.splits) - 1) in steps
     assert all(0 <= j < len(plans[p_i].splits) for p_i, j in steps)
-    # a spider with three equal legs: the leg's tables are computed once
+    # a spider with three equal legs, planned without sharing: the multi-template count computes
+    # the leg's tables once
     legs = [(0, 1), (1, 2), (0, 3), (3, 4), (0, 5), (5, 6)]
-    p = cc.Plan(np.array(legs, dtype=np.int32), root=0, bind=False)
+    p = cc.Plan(np.array(legs, dtype=np.int32), root=0, bind=False, flags=cc.CC_PLAN_NO_SHARING)
     assert cc.Multi([p]).info["steps"] < len(p.splits)
     with pytest.raises(cc.CCError):
         cc.Multi([cc.Plan(inputs.path_tree(4), bind=False), cc.Plan(inputs.path_tree(5), bind=False)])

@@ -238,3 +238,18 @@ def test_estimate_tracks_true_count(dev):
     torch.cuda.synchronize()
     est, se = cc.estimate(P, X.cpu().numpy())
     assert abs(est - copies) < 5 * se
+
+
+def test_shared_and_unshared_plans_agree(dev):
+    """A template with equal branches: the plan that runs each equal branch once and the plan that
+    runs every split both match the oracle."""
+    cc = _cc()
+    legs = np.array([(0, 1), (1, 2), (0, 3), (3, 4), (0, 5), (5, 6), (6, 7)], dtype=np.int32)
+    rp, cl = inputs.rmat_graph(11, 16, 8)
+    col = inputs.colours(len(rp) - 1, 8, 9)
+    shared = cc.Plan(legs, root=0)
+    assert shared.info.n_splits < 7
+    print("case: spider k=8, shared and unshared plans", flush=True)
+    Xs, _, _ = check_case(rp, cl, col, legs, root=0, hub_threshold=64, chunk=64)
+    Xf, _, _ = check_case(rp, cl, col, legs, root=0, hub_threshold=64, chunk=64, flags=cc.CC_PLAN_NO_SHARING)
+    assert Xs == Xf or abs(Xs - Xf) <= 1e-12 * Xf
