@@ -89,7 +89,8 @@ cc_status cc_plan_create(int32_t k, const int32_t* edges_host, int32_t root, uin
 typedef struct {
     int32_t k;
     int32_t root;
-    int32_t n_splits;                 /* number of sub-template splits (k-1) */
+    int32_t n_splits;                 /* splits that run: k-1, fewer when equal sub-templates are
+                                         shared (CC_PLAN_NO_SHARING keeps all k-1) */
     double aut;                       /* |Aut(T)|, the automorphism count of T */
     int64_t units_per_edge;           /* colour-set-edge units per directed CSR entry, counted on
                                          the reference partition: sum over splits of C(k,p), p the
