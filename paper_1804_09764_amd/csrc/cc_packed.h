@@ -39,14 +39,48 @@ __device__ inline void stage_colours(const StepParams& S, int uvec, int cnt, int
     if (lane < cnt) {
         const uint8_t* src = S.colour + (int64_t)uvec * S.B + b0;
         uint8_t* dst = cs + lane * S.bt;
-        if (((S.B | b0 | nb | S.bt) & 3) == 0) {  // 4-byte aligned: four colourings per load
-            for (int q = 0; q < nb; q += 4)
-                *reinterpret_cast<uint32_t*>(dst + q) = *reinterpret_cast<const uint32_t*>(src + q);
+        if (((S.B | b0 | nb | S.bt) & 15) == 0) {  // 16 colourings per load, all loads in flight
+            uint4 w[kWave / 16];
+#pragma unroll
+            for (int q = 0; q < kWave / 16; ++q)
+                if (16 * q < nb) w[q] = *reinterpret_cast<const uint4*>(src + 16 * q);
+#pragma unroll
+            for (int q = 0; q < kWave / 16; ++q)
+                if (16 * q < nb) *reinterpret_cast<uint4*>(dst + 16 * q) = w[q];
+        } else if (((S.B | b0 | nb | S.bt) & 3) == 0) {  // four colourings per load
+            uint32_t w[kWave / 4];
+#pragma unroll
+            for (int q = 0; q < kWave / 4; ++q)
+                if (4 * q < nb) w[q] = *reinterpret_cast<const uint32_t*>(src + 4 * q);
+#pragma unroll
+            for (int q = 0; q < kWave / 4; ++q)
+                if (4 * q < nb) *reinterpret_cast<uint32_t*>(dst + 4 * q) = w[q];
         } else {
             for (int q = 0; q < nb; ++q) dst[q] = src[q];
         }
     }
     wave_sync_lds();
+}
+
+// active rows of v for the tile's colourings into LDS (a >= 2), eight loads in flight per lane;
+// issued before the neighbour sum, whose closing barrier orders them before the combine
+__device__ inline void pstage_a(const StepParams& S, int v, int b0, int nb, double* Ash, int lane) {
+    if (S.a < 2) return;
+    const double* arow = S.A + (int64_t)v * S.astride + (int64_t)b0 * S.Wa;
+    const int na = nb * S.Wa;
+    for (int i0 = 0; i0 < na; i0 += 8 * kWave) {
+        double a8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + q * kWave + lane;
+            a8[q] = i < na ? arow[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + q * kWave + lane;
+            if (i < na) Ash[i] = a8[q];
+        }
+    }
 }
 
 // rows of entries [g D, g D + D) of a block in flight: values and N targets (-1: nothing to add)
@@ -164,7 +198,7 @@ __device__ void pcount(const StepParams& S, int64_t beg, int64_t end, int b0, in
     }
 }
 
-// output rows of v for the tile's colourings from N (LDS) and v's active rows
+// output rows of v for the tile's colourings from N and v's active rows (both in LDS)
 __device__ inline void pcombine(const StepParams& S, int v, const uint8_t* cvrow, int b0, int nb, const double* N,
                                 double* Ash, const PMaps& M, int lane) {
     const uint16_t* eml = M.em;
@@ -180,22 +214,7 @@ __device__ inline void pcombine(const StepParams& S, int v, const uint8_t* cvrow
         }
         return;
     }
-    const double* arow = S.A + (int64_t)v * S.astride + (int64_t)b0 * S.Wa;
-    const int na = nb * S.Wa;
-    for (int i0 = 0; i0 < na; i0 += 4 * kWave) {  // four loads in flight per lane
-        double a4[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = i0 + q * kWave + lane;
-            a4[q] = i < na ? arow[i] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = i0 + q * kWave + lane;
-            if (i < na) Ash[i] = a4[q];
-        }
-    }
-    wave_sync_lds();
+    // the active rows are already in Ash (pstage_a)
     for (int f = lane; f < E; f += kWave) {
         const int bl = f / Ws, r = f - bl * Ws;
         const int cv = cvrow[bl];
@@ -231,6 +250,7 @@ __device__ void plight_row(const StepParams& S, int v, double* N, double* Ash, c
     const uint8_t* cvall = S.colour + (int64_t)v * S.B;
     for (int b0 = 0; b0 < S.B; b0 += S.bt) {
         const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
+        pstage_a(S, v, b0, nb, Ash, lane);
         for (int i = lane; i < nb * S.Cf; i += kWave) N[i] = 0.0;
         wave_sync_lds();
         if (beg < end) pneighbours<J, P1>(S, beg, end, cvall + b0, b0, nb, N, M, lane);
@@ -270,6 +290,7 @@ __device__ inline void do_phub(const StepParams& S, int64_t t, double* N, double
     const uint8_t* cvall = S.colour + (int64_t)h.v * S.B;
     for (int b0 = 0; b0 < S.B; b0 += S.bt) {
         const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
+        pstage_a(S, h.v, b0, nb, Ash, lane);
         for (int i = lane; i < nb * S.Cf; i += kWave) {
             double sum = 0.0;
             const double* pp = S.partial + h.first_chunk * S.nstride + (int64_t)b0 * S.Cf + i;

@@ -108,12 +108,14 @@ void packed_tile(StepParams* S) {
     int J = 1;
     while (J < 8 && kWave * J < bt * width) J <<= 1;
     S->pJ = J;
-    S->a_off = bt * S->Cf;
-    S->tg_off = S->a_off + (S->a >= 2 ? bt * S->Wa : 0);
-    S->cs_off = S->tg_off + (S->p >= 2 ? J * S->k * kWave / 4 : 0);
-    S->lds_wave = S->cs_off + (kWave * bt + 7) / 8;
+    // every offset is even (16-byte aligned) so that the colour stage takes 16-byte LDS stores
+    auto even = [](int x) { return (x + 1) & ~1; };
+    S->a_off = even(bt * S->Cf);
+    S->tg_off = even(S->a_off + (S->a >= 2 ? bt * S->Wa : 0));
+    S->cs_off = even(S->tg_off + (S->p >= 2 ? J * S->k * kWave / 4 : 0));
+    S->lds_wave = even(S->cs_off + (kWave * bt + 7) / 8);
     S->tab_u16 = (S->a >= 2 ? 2 * S->npairs * S->Ws : 0) + (S->p >= 2 ? S->k * S->Wp : 0) + S->k * S->Nw;
-    S->tab_doubles = (S->tab_u16 + 3) / 4;
+    S->tab_doubles = even((S->tab_u16 + 3) / 4);
 }
 
 size_t packed_lds_bytes(const StepParams& S, int waves) {
