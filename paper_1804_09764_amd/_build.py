@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcc.so")
-SOURCES = ["cc_kernels.hip", "cc_packed.hip", "cc_plan.cpp", "cc_api.cpp"]
+SOURCES = ["cc_kernels.hip", "cc_packed.hip", "cc_plan.cpp", "cc_api.cpp", "cc_multi.cpp", "cc_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept out of every HIP build.
@@ -17,7 +17,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 
 
 def sources() -> list[str]:
-    headers = [os.path.join(CSRC, h) for h in ("cc_internal.h", "cc_device.h", "cc_packed.h")]
+    headers = [os.path.join(CSRC, h) for h in ("cc_internal.h", "cc_device.h", "cc_packed.h", "cc_host.h")]
     return [os.path.join(CSRC, s) for s in SOURCES] + headers + [os.path.join(os.path.dirname(PKG), "include", "cc.h")]
 
 

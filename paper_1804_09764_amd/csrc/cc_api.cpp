@@ -1,5 +1,6 @@
-// Host side of the C ABI declared in include/cc.h: argument checking, workspace layout, work-list
-// construction and the launch sequence of one count.
+// Host side of the C ABI declared in include/cc.h: plans, graphs, colouring, plain and packed counts,
+// estimates and measurement; argument checking, workspace layouts, work lists and launch sequences.
+// Multi-template counts are in cc_multi.cpp, instance batches in cc_batch.cpp.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -12,9 +13,11 @@
 #include <string>
 #include <vector>
 
+#include "cc_host.h"
 #include "cc_internal.h"
 
-namespace {
+namespace cc {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -27,10 +30,6 @@ cc_status hip_fail(hipError_t e, const char* what) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
     return CC_EDEVICE;
 }
-
-inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
-
-inline int64_t pad32(int64_t n) { return (n + 31) / 32 * 32; }
 
 void resolve_tuning(int64_t nnz, const cc_tuning* t, int32_t* thr, int32_t* chunk, int32_t* cols = nullptr) {
     int32_t c = (t && t->chunk > 0) ? t->chunk : (nnz >= ((int64_t)1 << 28) ? 2048 : 512);
@@ -78,14 +77,6 @@ CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
 }
 
 // workspace of a packed count with B colourings per row
-struct PackedLayout {
-    size_t arena_off, partial_off, root_off, colour_off, red_off, total;
-    int64_t n_pad, nstride;
-    std::vector<int64_t> col_off;  // per table, in columns of n_pad doubles
-    std::vector<int64_t> stride;   // per table: doubles between consecutive vertices
-    std::vector<int64_t> bstep;    // per table: doubles between consecutive colourings
-};
-
 PackedLayout packed_layout(const cc_plan* P, const cc_graph* G, int32_t B) {
     PackedLayout L;
     L.n_pad = pad32(G->n);
@@ -102,55 +93,6 @@ PackedLayout packed_layout(const cc_plan* P, const cc_graph* G, int32_t B) {
     L.nstride = nst;
     L.arena_off = 0;
     L.partial_off = align256((size_t)cols * (size_t)L.n_pad * sizeof(double));
-    L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)nst * sizeof(double));
-    L.colour_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * (size_t)B * sizeof(double));
-    L.red_off = align256(L.colour_off + (size_t)std::max<int64_t>(G->n, 1) * (size_t)B);
-    L.total = align256(L.red_off + (size_t)cc::packed_reduce_blocks(G->n) * (size_t)B * sizeof(double));
-    return L;
-}
-
-// workspace of a packed multi-template count: the steps' allocation sequence replayed over the
-// shared tables
-PackedLayout multi_layout(const cc_multi* M, const cc_graph* G, int32_t B) {
-    PackedLayout L;
-    L.n_pad = pad32(G->n);
-    const size_t nt = M->table_W.size();
-    L.col_off.assign(nt, 0);
-    L.stride.resize(nt);
-    L.bstep.resize(nt);
-    for (size_t t = 0; t < nt; ++t) {
-        const int64_t W = M->table_W[t];
-        L.stride[t] = cc::packed_wide(W) ? cc::packed_stride(W) : cc::packed_stride((int64_t)B * W);
-        L.bstep[t] = cc::packed_wide(W) ? L.n_pad * cc::packed_stride(W) : W;
-    }
-    // first-fit over columns, in step order
-    std::vector<std::pair<int64_t, int64_t>> used;
-    int64_t peak = 0, nst = 1;
-    for (const auto& st : M->steps) {
-        const cc::Split& sp = M->plans[(size_t)st.plan]->splits[(size_t)st.split];
-        nst = std::max(nst, cc::packed_stride((int64_t)B * sp.Cf));
-        if (st.out >= 0) {
-            const int64_t len = cc::packed_cols(M->table_W[(size_t)st.out], B);
-            std::sort(used.begin(), used.end());
-            int64_t off = 0;
-            for (auto& u : used) {
-                if (u.first - off >= len) break;
-                off = std::max(off, u.first + u.second);
-            }
-            used.push_back({off, len});
-            peak = std::max(peak, off + len);
-            L.col_off[(size_t)st.out] = off;
-        }
-        for (int g : st.release)
-            for (size_t i = 0; i < used.size(); ++i)
-                if (used[i].first == L.col_off[(size_t)g]) {
-                    used.erase(used.begin() + (long)i);
-                    break;
-                }
-    }
-    L.nstride = nst;
-    L.arena_off = 0;
-    L.partial_off = align256((size_t)peak * (size_t)L.n_pad * sizeof(double));
     L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)nst * sizeof(double));
     L.colour_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * (size_t)B * sizeof(double));
     L.red_off = align256(L.colour_off + (size_t)std::max<int64_t>(G->n, 1) * (size_t)B);
@@ -219,14 +161,6 @@ cc::StepParams step_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     }
     return h;
 }
-
-// the tables of one split in a packed layout: ids into PackedLayout (-1: a single vertex; out -2:
-// the template's root counts)
-struct PIds {
-    int act, pas, out;
-};
-
-PIds own_ids(const cc::Split& sp) { return PIds{sp.act, sp.pas, sp.out}; }
 
 // the same split over the packed layout (B colourings per row, colours as [v][b])
 cc::StepParams packed_step_params(const cc_plan* P, const cc_graph* G, const cc::Split& sp, PIds t,
@@ -305,7 +239,10 @@ bool packed_fits(const cc_plan* P, int32_t B) {
     return true;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace cc
+
+using namespace cc::host;
 
 extern "C" {
 
@@ -715,376 +652,12 @@ cc_status cc_count_packed(const cc_plan* P, const cc_graph* G, const uint8_t* co
     return CC_OK;
 }
 
-cc_status cc_multi_create(int32_t n_plans, const cc_plan* const* plans, cc_multi** out) {
-    if (!out) return fail(CC_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (n_plans < 1 || !plans) return fail(CC_EINVAL, "need at least one plan");
-    for (int32_t i = 0; i < n_plans; ++i) {
-        if (!plans[i]) return fail(CC_EINVAL, "NULL plan");
-        if (plans[i]->k != plans[0]->k) return fail(CC_EINVAL, "all plans of a multi-template count need the same k");
-    }
-    cc_multi* M = new (std::nothrow) cc_multi();
-    if (!M) return fail(CC_ENOMEM, "allocation failed");
-    try {
-        M->k = plans[0]->k;
-        M->plans.assign(plans, plans + n_plans);
-        std::map<std::string, int> key_to_g;
-        for (int32_t p = 0; p < n_plans; ++p) {
-            const cc_plan* P = plans[p];
-            M->n_splits += (int64_t)P->splits.size();
-            if (P->splits.empty()) continue;
-            std::vector<int> producer(P->tables.size(), -1);
-            for (size_t j = 0; j < P->splits.size(); ++j)
-                if (P->splits[j].out >= 0) producer[(size_t)P->splits[j].out] = (int)j;
-            // a table's global id, computing it (after its inputs, in the plan's own order) unless
-            // an equal rooted sub-template was computed before
-            std::function<int(int)> need = [&](int t) -> int {
-                const std::string& key = P->tables[(size_t)t].key;
-                auto it = key_to_g.find(key);
-                if (it != key_to_g.end()) return it->second;
-                const int j = producer[(size_t)t];
-                const cc::Split& sp = P->splits[(size_t)j];
-                const int a = sp.act >= 0 ? need(sp.act) : -1;
-                const int q = sp.pas >= 0 ? need(sp.pas) : -1;
-                const int g = (int)M->table_W.size();
-                M->table_W.push_back(P->tables[(size_t)t].W);
-                key_to_g[key] = g;
-                M->steps.push_back(cc_multi::Step{(int)p, j, a, q, g, {}});
-                return g;
-            };
-            const int jr = (int)P->splits.size() - 1;  // the root split comes last
-            const cc::Split& sr = P->splits[(size_t)jr];
-            const int a = sr.act >= 0 ? need(sr.act) : -1;
-            const int q = sr.pas >= 0 ? need(sr.pas) : -1;
-            M->steps.push_back(cc_multi::Step{(int)p, jr, a, q, -2, {}});
-        }
-        std::vector<int> last(M->table_W.size(), -1);
-        for (size_t i = 0; i < M->steps.size(); ++i) {
-            if (M->steps[i].act >= 0) last[(size_t)M->steps[i].act] = (int)i;
-            if (M->steps[i].pas >= 0) last[(size_t)M->steps[i].pas] = (int)i;
-        }
-        for (size_t g = 0; g < last.size(); ++g)
-            if (last[g] >= 0) M->steps[(size_t)last[g]].release.push_back((int)g);
-    } catch (const std::bad_alloc&) {
-        delete M;
-        return fail(CC_ENOMEM, "host allocation failed");
-    }
-    *out = M;
-    return CC_OK;
-}
-
-cc_status cc_multi_info_get(const cc_multi* M, int32_t* n_steps, int64_t* n_splits, int32_t* n_tables) {
-    if (!M) return fail(CC_EINVAL, "NULL multi");
-    if (n_steps) *n_steps = (int32_t)M->steps.size();
-    if (n_splits) *n_splits = M->n_splits;
-    if (n_tables) *n_tables = (int32_t)M->table_W.size();
-    return CC_OK;
-}
-
-cc_status cc_multi_step_get(const cc_multi* M, int32_t i, int32_t* plan, int32_t* split) {
-    if (!M || !plan || !split) return fail(CC_EINVAL, "NULL argument");
-    if (i < 0 || (size_t)i >= M->steps.size()) return fail(CC_ERANGE, "step index out of range");
-    *plan = M->steps[(size_t)i].plan;
-    *split = M->steps[(size_t)i].split;
-    return CC_OK;
-}
-
-void cc_multi_destroy(cc_multi* M) { delete M; }
-
-cc_status cc_count_packed_multi_workspace_bytes(const cc_multi* M, const cc_graph* G, int32_t B, size_t* bytes) {
-    if (!M || !G || !bytes) return fail(CC_EINVAL, "NULL argument");
-    if (B < 1 || B > CC_MAX_PACKED) return fail(CC_ERANGE, "B must be in [1, CC_MAX_PACKED]");
-    *bytes = multi_layout(M, G, B).total;
-    return CC_OK;
-}
-
-cc_status cc_count_packed_multi(const cc_multi* M, const cc_graph* G, const uint8_t* colours_dev, int32_t B,
-                                void* ws_dev, size_t ws_bytes, double* X_dev, void* stream) {
-    if (!M || !G) return fail(CC_EINVAL, "NULL multi or graph");
-    if (B < 1 || B > CC_MAX_PACKED) return fail(CC_ERANGE, "B must be in [1, CC_MAX_PACKED]");
-    if (!X_dev || !ws_dev || (G->n > 0 && !colours_dev)) return fail(CC_EINVAL, "NULL buffer");
-    for (const cc_plan* P : M->plans) {
-        if (!P->splits.empty() && !P->dev) return fail(CC_EINVAL, "plan not bound to device memory");
-        if (!packed_fits(P, B)) return fail(CC_ERANGE, "template too large for the packed layout (use cc_count)");
-    }
-    PackedLayout L = multi_layout(M, G, B);
-    if (ws_bytes < L.total) return fail(CC_ENOSPC, "count workspace too small");
-    hipStream_t st = (hipStream_t)stream;
-    uint8_t* ws = (uint8_t*)ws_dev;
-    const int64_t n = G->n;
-    const int32_t np = (int32_t)M->plans.size();
-    hipError_t e = hipSuccess;
-    if (n == 0) {
-        e = cc::launch_fill_f64(X_dev, (int64_t)np * B, 0.0, st);
-        if (e != hipSuccess) return hip_fail(e, "fill");
-        return CC_OK;
-    }
-    double* arena = (double*)(ws + L.arena_off);
-    double* partial = (double*)(ws + L.partial_off);
-    double* root_out = (double*)(ws + L.root_off);
-    uint8_t* cpk = ws + L.colour_off;
-    double* red = (double*)(ws + L.red_off);
-    e = cc::launch_transpose_colours(colours_dev, n, B, cpk, st);
-    // single-vertex templates: every vertex roots one map
-    for (int32_t p = 0; e == hipSuccess && p < np; ++p)
-        if (M->plans[(size_t)p]->splits.empty()) {
-            e = cc::launch_fill_f64(root_out, n * B, 1.0, st);
-            if (e == hipSuccess) e = cc::launch_reduce_packed(root_out, n, B, red, X_dev + (int64_t)p * B, st);
-        }
-    for (size_t i = 0; e == hipSuccess && i < M->steps.size(); ++i) {
-        const cc_multi::Step& S = M->steps[i];
-        const cc_plan* P = M->plans[(size_t)S.plan];
-        const cc::Split& sp = P->splits[(size_t)S.split];
-        const PIds ids{S.act, S.pas, S.out};
-        if (cc::packed_kernel_split(sp)) {
-            cc::StepParams h = packed_step_params(P, G, sp, ids, cpk, arena, L, partial, root_out, B);
-            e = cc::launch_packed_split(h, G->n_cu, st, nullptr);
-        } else {
-            for (int32_t b = 0; e == hipSuccess && b < B; ++b) {
-                cc::StepParams h = packed_one_params(P, G, sp, ids, colours_dev, arena, L, partial, root_out, B, b);
-                e = cc::launch_split(h, G->n_cu, st, nullptr);
-            }
-        }
-        if (e == hipSuccess && S.out == -2)
-            e = cc::launch_reduce_packed(root_out, n, B, red, X_dev + (int64_t)S.plan * B, st);
-    }
-    if (e != hipSuccess) return hip_fail(e, "packed multi-template count launch");
-    return CC_OK;
-}
-
-cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flags, cc_batch** out) {
-    if (!out) return fail(CC_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(CC_EINVAL, "bad instance array");
-    cc_batch* B = new (std::nothrow) cc_batch();
-    if (!B) return fail(CC_ENOMEM, "batch allocation failed");
-    B->flags = flags;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
-    try {
-        B->inst.resize((size_t)n_inst);
-        std::vector<std::vector<int>> seg_of;  // per instance: final segment of each split
-        std::vector<cc_batch::Seg> segs;
-        for (int32_t i = 0; i < n_inst; ++i) {
-            const cc_instance& in = inst[i];
-            if (!in.plan || !in.graph || !in.X_dev || (in.graph->n > 0 && !in.colours_dev)) {
-                delete B;
-                return fail(CC_EINVAL, "instance " + std::to_string(i) + ": NULL plan, graph or buffer");
-            }
-            if (!in.plan->splits.empty() && !in.plan->dev) {
-                delete B;
-                return fail(CC_EINVAL, "instance " + std::to_string(i) + ": plan not bound to device memory");
-            }
-            const cc_plan* P = in.plan;
-            const cc_graph* G = in.graph;
-            if (B->n_cu == 0) B->n_cu = G->n_cu;
-            cc_batch::Inst& I = B->inst[(size_t)i];
-            I.in = in;
-            const int64_t n_pad = pad32(G->n);
-            I.arena_off = take((size_t)P->arena_cols * (size_t)n_pad * sizeof(double));
-            I.partial_off = take((size_t)G->n_chunks * (size_t)P->max_stride_N * sizeof(double));
-            I.root_off = in.vertex_dev ? 0 : take((size_t)std::max<int64_t>(G->n, 1) * sizeof(double));
-            I.red_off = take(1024 * sizeof(double));
-            B->max_red_blocks = std::max(B->max_red_blocks, cc::reduce_blocks_for(G->n));
-            if (G->n == 0) continue;
-            // segments of this instance in plan order, each waiting for the previous one: the
-            // instance's splits share its table arena (first-fit reuse) and its chunk-partial
-            // scratch, so a split may overwrite what an earlier split reads; running them in plan
-            // order, as a plain count does, removes every such hazard. Instances run side by side.
-            std::vector<int> last(P->splits.size(), -1);
-            for (size_t j = 0; j < P->splits.size(); ++j) {
-                const cc::Split& sp = P->splits[j];
-                cc_batch::Seg a{};
-                a.inst = i;
-                a.split = (int)j;
-                a.phase = 0;
-                a.n_items = G->n_chunks + G->n_ranges;
-                a.ndep = 0;
-                a.level = 0;
-                if (j > 0) {
-                    const int d = last[j - 1];
-                    a.dep[a.ndep++] = d;
-                    a.level = segs[(size_t)d].level + 1;
-                }
-                segs.push_back(a);
-                last[j] = (int)segs.size() - 1;
-                if (G->n_hubs > 0) {
-                    cc_batch::Seg h{};
-                    h.inst = i;
-                    h.split = (int)j;
-                    h.phase = 1;
-                    h.n_items = G->n_hubs;
-                    h.ndep = 1;
-                    h.dep[0] = last[j];
-                    h.level = a.level + 1;
-                    segs.push_back(h);
-                    last[j] = (int)segs.size() - 1;
-                }
-                if (sp.p >= 2)
-                    B->J = std::max(B->J, cc::pick_J(sp.Wp, G->cols_per_lane));
-                B->lds_wave = std::max(B->lds_wave, cc::split_lds_wave(sp.Nw, sp.Wa, sp.a));
-                // level mode launches each split's tasks with the kernel a plain count uses
-                // (all variants sum in the same order); cut-row finishes run in variant 0
-                const int var = cc::split_variant(sp.p, sp.Wp, G->cols_per_lane);
-                const int base = cc::split_lds_wave(sp.Nw, sp.Wa, sp.a);
-                for (size_t q = (size_t)(G->n_hubs > 0 ? last[j] - 1 : last[j]); q <= (size_t)last[j]; ++q) {
-                    segs[q].variant = segs[q].phase == 0 ? var : 0;
-                    segs[q].lds_wave = base + (segs[q].phase == 0 ? cc::variant_stage(var) : 0);
-                }
-            }
-        }
-        // instance-major order (as built) for the persistent launch; level order for the
-        // level-by-level launches (stable: instance, split, phase within a level)
-        B->segs = segs;
-        B->ranges.assign((size_t)n_inst, cc::SegRange{0, 0});
-        for (size_t q = 0; q < segs.size(); ++q) {
-            cc::SegRange& r = B->ranges[(size_t)segs[q].inst];
-            if (r.count == 0) r.first = (int32_t)q;
-            r.count++;
-        }
-        B->level_order.resize(segs.size());
-        for (size_t q = 0; q < segs.size(); ++q) B->level_order[q] = (int)q;
-        std::stable_sort(B->level_order.begin(), B->level_order.end(), [&](int x, int y) {
-            const cc_batch::Seg &a = segs[(size_t)x], &b = segs[(size_t)y];
-            return a.level != b.level ? a.level < b.level : a.variant < b.variant;
-        });
-        B->groups.clear();
-        int64_t item = 0;
-        for (size_t q = 0; q < B->level_order.size(); ++q) {
-            const cc_batch::Seg& sg = segs[(size_t)B->level_order[q]];
-            if (B->groups.empty() || segs[(size_t)B->level_order[(size_t)B->groups.back().seg_lo]].level != sg.level ||
-                B->groups.back().variant != sg.variant)
-                B->groups.push_back(cc_batch::Group{(int)q, (int)q, sg.variant, 16, item, item});
-            cc_batch::Group& g = B->groups.back();
-            g.seg_hi = (int)q + 1;
-            g.item_hi = item + sg.n_items;
-            g.lds_wave = std::max(g.lds_wave, sg.lds_wave);
-            item += sg.n_items;
-        }
-        if (B->lds_wave == 0) B->lds_wave = 16;
-        const size_t nseg = std::max<size_t>(B->segs.size(), 1);
-        B->seg_off = take(nseg * sizeof(cc::SegDesc));
-        B->seg_level_off = take(nseg * sizeof(cc::SegDesc));
-        B->range_off = take(std::max<size_t>((size_t)n_inst, 1) * sizeof(cc::SegRange));
-        B->rd_off = take(std::max<size_t>((size_t)n_inst, 1) * sizeof(cc::ReduceDesc));
-        B->total = off;
-        B->seg_host.resize(B->segs.size());
-        B->seg_level_host.resize(B->segs.size());
-        B->rd_host.resize((size_t)n_inst);
-    } catch (const std::bad_alloc&) {
-        delete B;
-        return fail(CC_ENOMEM, "host allocation failed while preparing the batch");
-    }
-    *out = B;
-    return CC_OK;
-}
-
-cc_status cc_batch_workspace_bytes(const cc_batch* B, size_t* bytes) {
-    if (!B || !bytes) return fail(CC_EINVAL, "NULL argument");
-    *bytes = B->total;
-    return CC_OK;
-}
-
-cc_status cc_batch_run(cc_batch* B, void* ws_dev, size_t ws_bytes, void* stream) {
-    if (!B || (!ws_dev && B->total > 0)) return fail(CC_EINVAL, "NULL argument");
-    if (ws_bytes < B->total) return fail(CC_ENOSPC, "batch workspace too small");
-    if (B->inst.empty()) return CC_OK;
-    hipStream_t st = (hipStream_t)stream;
-    uint8_t* ws = (uint8_t*)ws_dev;
-    cc::SegDesc* seg_dev = (cc::SegDesc*)(ws + B->seg_off);
-    cc::SegDesc* seg_level_dev = (cc::SegDesc*)(ws + B->seg_level_off);
-    cc::SegRange* range_dev = (cc::SegRange*)(ws + B->range_off);
-    cc::ReduceDesc* rd_dev = (cc::ReduceDesc*)(ws + B->rd_off);
-    for (size_t q = 0; q < B->segs.size(); ++q) {
-        const cc_batch::Seg& sg = B->segs[q];
-        const cc_batch::Inst& I = B->inst[(size_t)sg.inst];
-        const cc_plan* P = I.in.plan;
-        const cc_graph* G = I.in.graph;
-        double* root_out = I.in.vertex_dev ? I.in.vertex_dev : (double*)(ws + I.root_off);
-        cc::SegDesc& D = B->seg_host[q];
-        D = cc::SegDesc{};
-        D.S = step_params(P, G, P->splits[(size_t)sg.split], I.in.colours_dev, (double*)(ws + I.arena_off),
-                          pad32(G->n), (double*)(ws + I.partial_off), root_out);
-        D.item_start = 0;
-        D.n_items = sg.n_items;
-        D.phase = sg.phase;
-    }
-    int64_t item = 0;
-    for (size_t q = 0; q < B->level_order.size(); ++q) {
-        cc::SegDesc& D = B->seg_level_host[q];
-        D = B->seg_host[(size_t)B->level_order[q]];
-        D.item_start = item;
-        D.S.stage_off = cc::split_lds_wave(D.S.Nw, D.S.Wa, D.S.a);  // narrow stage after N and A rows
-        item += D.n_items;
-    }
-    for (size_t i = 0; i < B->inst.size(); ++i) {
-        const cc_batch::Inst& I = B->inst[i];
-        cc::ReduceDesc& R = B->rd_host[i];
-        R.x = I.in.vertex_dev ? I.in.vertex_dev : (const double*)(ws + I.root_off);
-        R.n = I.in.graph->n;
-        R.out = I.in.X_dev;
-        R.partial = (double*)(ws + I.red_off);
-    }
-    const bool levels = (B->flags & CC_BATCH_LEVELS) != 0;
-    hipError_t e = hipSuccess;
-    if (!B->segs.empty()) {
-        if (levels)
-            e = hipMemcpyAsync(seg_level_dev, B->seg_level_host.data(), B->seg_level_host.size() * sizeof(cc::SegDesc),
-                               hipMemcpyHostToDevice, st);
-        else
-            e = hipMemcpyAsync(seg_dev, B->seg_host.data(), B->seg_host.size() * sizeof(cc::SegDesc),
-                               hipMemcpyHostToDevice, st);
-        if (e == hipSuccess && !levels)
-            e = hipMemcpyAsync(range_dev, B->ranges.data(), B->ranges.size() * sizeof(cc::SegRange),
-                               hipMemcpyHostToDevice, st);
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(rd_dev, B->rd_host.data(), B->rd_host.size() * sizeof(cc::ReduceDesc), hipMemcpyHostToDevice, st);
-    // instances without splits (k = 1): every vertex roots one map
-    for (size_t i = 0; e == hipSuccess && i < B->inst.size(); ++i) {
-        const cc_batch::Inst& I = B->inst[i];
-        if (I.in.graph->n > 0 && I.in.plan->splits.empty())
-            e = cc::launch_fill_f64(const_cast<double*>(B->rd_host[i].x), I.in.graph->n, 1.0, st);
-    }
-    if (e == hipSuccess && !B->segs.empty()) {
-        if (levels) {
-            for (size_t l = 0; e == hipSuccess && l < B->groups.size(); ++l) {
-                const cc_batch::Group& g = B->groups[l];
-                e = cc::launch_batch_level(seg_level_dev, g.seg_lo, g.seg_hi, g.item_lo, g.item_hi, g.variant, g.lds_wave,
-                                           B->n_cu, st);
-            }
-        } else {
-            e = cc::launch_batch_inst(seg_dev, range_dev, (int)B->inst.size(), B->J, B->lds_wave, B->n_cu,
-                                      (int)((B->flags >> 8) & 0xFFu), st);
-        }
-    }
-    for (size_t i = 0; e == hipSuccess && i < B->inst.size(); ++i)
-        if (B->inst[i].in.graph->n == 0) e = cc::launch_fill_f64(B->inst[i].in.X_dev, 1, 0.0, st);
-    if (e == hipSuccess) e = cc::launch_reduce_batch(rd_dev, (int)B->inst.size(), B->max_red_blocks, st);
-    if (e != hipSuccess) return hip_fail(e, "batch launch");
-    return CC_OK;
-}
-
 cc_status cc_stream_check(void* stream) {
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "stream check");
     return CC_OK;
 }
-
-cc_status cc_batch_check(cc_batch* B, void* stream) {
-    if (!B) return fail(CC_EINVAL, "NULL batch");
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "batch check");
-    return CC_OK;
-}
-
-void cc_batch_destroy(cc_batch* B) { delete B; }
 
 static long double scale_factor(const cc_plan* P) {
     long double s = 1.0L;
