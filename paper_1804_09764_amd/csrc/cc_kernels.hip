@@ -637,12 +637,14 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n
     return hipGetLastError();
 }
 
-// passive-row doubles per lane per pass
+// passive-row doubles per lane per pass: the narrowest pass that covers the row, up to 8 (wider
+// rows take several passes; eight doubles per lane measured faster than four from 330 up)
 int pick_J(int Wp, int want) {
     if (want == 1 || want == 2 || want == 4 || want == 8) return want;
     if (Wp <= 64) return 1;
     if (Wp <= 128) return 2;
-    return 4;
+    if (Wp <= 256) return 4;
+    return 8;
 }
 
 // wavefronts per workgroup (4, 2 or 1; a workgroup stays within 64 KB of LDS): a smaller
