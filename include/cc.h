@@ -128,7 +128,7 @@ typedef struct cc_graph cc_graph;
 typedef struct {
     int32_t hub_threshold;  /* rows with more neighbours than this are cut into chunks (0 = auto) */
     int32_t chunk;          /* neighbours per chunk of a cut row (0 = auto; multiple of 64) */
-    int32_t cols_per_lane;  /* passive-row doubles each lane holds per pass: 1, 2, 4 or 8 (0 = auto) */
+    int32_t cols_per_lane;  /* passive-row doubles each lane holds per pass: 1, 2, 4, 8 or 16 (0 = auto) */
 } cc_tuning;
 
 /* flags for cc_graph_prepare */

@@ -380,8 +380,8 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     if (n >= ((int64_t)1 << 31)) return fail(CC_ERANGE, "n must be below 2^31");
     int32_t thr, chunk, cols;
     resolve_tuning(nnz, tuning, &thr, &chunk, &cols);
-    if (cols != 0 && cols != 1 && cols != 2 && cols != 4 && cols != 8)
-        return fail(CC_EINVAL, "cols_per_lane must be 0, 1, 2, 4 or 8");
+    if (cols != 0 && cols != 1 && cols != 2 && cols != 4 && cols != 8 && cols != 16)
+        return fail(CC_EINVAL, "cols_per_lane must be 0, 1, 2, 4, 8 or 16");
     GraphLayout L = graph_layout(n, nnz, thr, chunk);
     if (ws_bytes < L.total) return fail(CC_ENOSPC, "graph workspace too small");
     hipStream_t st = (hipStream_t)stream;

@@ -101,7 +101,7 @@ __device__ __forceinline__ void consume_batch(int b, int cnt, int sc, int& cur, 
 
 template <int J>
 __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
-    constexpr int D = (J >= 8) ? 2 : 4;  // rows per batch: keeps two batches within the VGPR budget
+    constexpr int D = (J >= 16) ? 1 : (J >= 8) ? 2 : 4;  // rows per batch: two batches within the VGPR budget
     const int k = S.k;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
@@ -265,7 +265,22 @@ __device__ __forceinline__ void combine_sets(const StepParams& S, double* orow, 
         for (int r = lane; r < S.Ws; r += kWave) {
             double sum = 0.0;
             const uint32_t* sp = S.split + r;
-            for (int j = 0; j < S.npairs; ++j) {
+            int j = 0;
+            // four pairs' loads in flight, then their products added in pair order
+            for (; j + 4 <= S.npairs; j += 4) {
+                uint32_t pr[4];
+                double av[4], nv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pr[q] = sp[(int64_t)(j + q) * S.Ws];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    av[q] = A[pr[q] & 0xFFFFu];
+                    nv[q] = N[pr[q] >> 16];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sum += av[q] * nv[q];
+            }
+            for (; j < S.npairs; ++j) {
                 const uint32_t pr = sp[(int64_t)j * S.Ws];
                 sum += A[pr & 0xFFFFu] * N[pr >> 16];
             }
@@ -677,7 +692,9 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
     const int threads = waves_per_block * kWave;
     S.waves_per_block = waves_per_block;
     const size_t lds = (size_t)S.lds_wave * waves_per_block * sizeof(double);
-    const int J = (S.p >= 2) ? pick_J(S.Wp, S.cols_per_lane) : 1;
+    int J = (S.p >= 2) ? pick_J(S.Wp, S.cols_per_lane) : 1;
+    // rows beyond 512 entries: 16 doubles per lane (one row in flight per batch), half the passes
+    if (S.p >= 2 && ((J == 8 && S.cols_per_lane == 0 && S.Wp > 512) || S.cols_per_lane == 16)) J = 16;
     const void* fn = nullptr;
     if (narrow == 16) fn = (const void*)k_split<1, 16>;
     else if (narrow == 32) fn = (const void*)k_split<1, 32>;
@@ -685,7 +702,8 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
         case 1: fn = (const void*)k_split<1, 0>; break;
         case 2: fn = (const void*)k_split<2, 0>; break;
         case 4: fn = (const void*)k_split<4, 0>; break;
-        default: fn = (const void*)k_split<8, 0>; break;
+        case 8: fn = (const void*)k_split<8, 0>; break;
+        default: fn = (const void*)k_split<16, 0>; break;
     }
     int per_cu = 0;
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
