@@ -70,11 +70,15 @@ __device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, 
 
 template <int J>
 __device__ __forceinline__ void fold_acc(double* N, const double (&acc)[J], const int (&f)[J]) {
-    // one LDS add per entry (ds_add_f64, no read back): a wavefront's LDS operations complete in
-    // issue order and one colour's targets are distinct, so each entry's order is unchanged
+    // wide rows: one LDS add per entry (ds_add_f64, no read back; a wavefront's LDS operations
+    // complete in issue order and one colour's targets are distinct, so each entry's order is
+    // unchanged); narrow rows: read, add, write (measured faster there)
 #pragma unroll
     for (int t = 0; t < J; ++t)
-        if (f[t] != (int)kNoSlot) __hip_atomic_fetch_add(N + f[t], acc[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (f[t] != (int)kNoSlot) {
+            if constexpr (J >= 4) __hip_atomic_fetch_add(N + f[t], acc[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            else N[f[t]] += acc[t];
+        }
 }
 
 template <int J, int D>
