@@ -107,7 +107,7 @@ __device__ __forceinline__ void consume_batch(int b, int cnt, int sc, int& cur, 
 
 template <int J>
 __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
-    constexpr int D = (J >= 16) ? 1 : (J >= 8) ? 2 : 4;  // rows per batch: two batches within the VGPR budget
+    constexpr int D = (J >= 16) ? 1 : (J >= 6) ? 2 : 4;  // rows per batch: two batches within the VGPR budget
     const int k = S.k;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
@@ -668,6 +668,16 @@ int pick_J(int Wp, int want) {
     return 8;
 }
 
+// the one-colouring launch may also take 6 doubles per lane (rows of 257..384 entries in one pass
+// with fewer idle lanes) or 16 (rows beyond 512 entries)
+static int launch_J(int Wp, int want) {
+    if (want == 16) return 16;
+    const int J = pick_J(Wp, want);
+    if (want == 0 && J == 8 && Wp <= 384) return 6;
+    if (want == 0 && J == 8 && Wp > 512) return 16;
+    return J;
+}
+
 // wavefronts per workgroup (4, 2 or 1; a workgroup stays within 64 KB of LDS): a smaller
 // workgroup only when it keeps over 10 % more wavefronts resident in a CU's 160 KB of LDS
 static int waves_for_lds(int lds_wave) {
@@ -698,9 +708,7 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
     const int threads = waves_per_block * kWave;
     S.waves_per_block = waves_per_block;
     const size_t lds = (size_t)S.lds_wave * waves_per_block * sizeof(double);
-    int J = (S.p >= 2) ? pick_J(S.Wp, S.cols_per_lane) : 1;
-    // rows beyond 512 entries: 16 doubles per lane (one row in flight per batch), half the passes
-    if (S.p >= 2 && ((J == 8 && S.cols_per_lane == 0 && S.Wp > 512) || S.cols_per_lane == 16)) J = 16;
+    const int J = (S.p >= 2) ? launch_J(S.Wp, S.cols_per_lane) : 1;
     const void* fn = nullptr;
     if (narrow == 16) fn = (const void*)k_split<1, 16>;
     else if (narrow == 32) fn = (const void*)k_split<1, 32>;
@@ -708,6 +716,7 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
         case 1: fn = (const void*)k_split<1, 0>; break;
         case 2: fn = (const void*)k_split<2, 0>; break;
         case 4: fn = (const void*)k_split<4, 0>; break;
+        case 6: fn = (const void*)k_split<6, 0>; break;
         case 8: fn = (const void*)k_split<8, 0>; break;
         default: fn = (const void*)k_split<16, 0>; break;
     }
