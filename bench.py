@@ -70,16 +70,33 @@ def split_bytes(k, s, a, p, n, nnz):
     return b
 
 
+def needed_lines(k, p):
+    """Expected number of 128-byte lines of a neighbour's colour-anchored passive row that hold at
+    least one entry the row needs. The row lists the (p-1)-sets over the neighbour's k-1 other
+    colours in colex order, 16 entries per line; an entry is needed unless its set holds the
+    row's colour, whose position among those k-1 colours is uniform."""
+    K = k - 1
+    masks = [m for m in range(1 << K) if bin(m).count("1") == p - 1]  # colex = increasing order
+    W = len(masks)
+    if W <= 16:
+        return 1.0
+    total = 0
+    for x in range(K):
+        total += sum(1 for l in range(0, W, 16) if any(not (masks[j] >> x) & 1 for j in range(l, min(l + 16, W))))
+    return total / K
+
+
 def loaded_bytes(k, s, a, p, n, nnz):
-    """Algorithmic bytes of one split launch: what its loads and stores must move through the
-    memory hierarchy. Per CSR entry: the column (4 B), the neighbour's colour (1 B) and, for the
-    expected fraction (k-1)/k of neighbours whose colour differs from the row's, the neighbour's
-    colour-anchored passive row (8 C(k-1, p-1) B, none when p = 1); per vertex: its row offsets,
-    colour, active row (a >= 2) and output row."""
+    """Algorithmic bytes of one split launch: what its loads and stores must move from HBM at the
+    128-byte line granularity of the layout. Per CSR entry: the column (4 B), the neighbour's
+    colour (1 B) and, for the expected fraction (k-1)/k of neighbours whose colour differs from
+    the row's, the lines of the neighbour's colour-anchored passive row that hold an entry the row
+    needs (entries whose set holds the row's colour are skipped; none when p = 1); per vertex: its
+    row offsets, colour, active row (a >= 2) and output row."""
     Wp, Wa, Ws = widths(k, s, a, p)
     b = 5 * nnz + 8 * (n + 1) + n + 8 * n * Ws + (8 * n * Wa if a >= 2 else 0)
     if p >= 2:
-        b += 8 * Wp * nnz * (k - 1) / k
+        b += 128 * needed_lines(k, p) * nnz * (k - 1) / k
     return b
 
 

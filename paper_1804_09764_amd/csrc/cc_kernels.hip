@@ -107,7 +107,7 @@ __device__ __forceinline__ void consume_batch(int b, int cnt, int sc, int& cur, 
 
 template <int J>
 __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
-    constexpr int D = (J >= 6) ? 1 : 4;  // rows per batch: two batches within the VGPR budget
+    constexpr int D = (J >= 6) ? 1 : (J >= 4) ? 2 : 4;  // rows per batch: two batches within the VGPR budget
     const int k = S.k;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
