@@ -73,13 +73,16 @@ def split_bytes(k, s, a, p, n, nnz):
 def needed_lines(k, p):
     """Expected number of 128-byte lines of a neighbour's colour-anchored passive row that hold at
     least one entry the row needs. The row lists the (p-1)-sets over the neighbour's k-1 other
-    colours in colex order, 16 entries per line; an entry is needed unless its set holds the
-    row's colour, whose position among those k-1 colours is uniform."""
+    colours in the library's storage order (cc_entry_order), 16 entries per line; an entry is
+    needed unless its set holds the row's colour, whose position among those k-1 colours is
+    uniform."""
     K = k - 1
-    masks = [m for m in range(1 << K) if bin(m).count("1") == p - 1]  # colex = increasing order
-    W = len(masks)
+    colex = [m for m in range(1 << K) if bin(m).count("1") == p - 1]  # colex = increasing order
+    W = len(colex)
     if W <= 16:
         return 1.0
+    import paper_1804_09764_amd as cc
+    masks = [colex[r] for r in cc.entry_order(k, p - 1)]
     total = 0
     for x in range(K):
         total += sum(1 for l in range(0, W, 16) if any(not (masks[j] >> x) & 1 for j in range(l, min(l + 16, W))))

@@ -118,6 +118,17 @@ cc_status cc_plan_bind_device(cc_plan* plan, void* dev, size_t bytes, void* stre
 
 void cc_plan_destroy(cc_plan* plan);
 
+/*
+ * Storage order of the entries of a colour-anchored table row (Section 2.1, Eq. 1: the counts
+ * C(v, T_i, S) of one vertex, S over the k colours): for templates on k vertices and sets holding
+ * m colours besides col(v), order[pos] receives the colex rank, over the k-1 other colours, of the
+ * set stored at position pos. Rows of more than 16 entries are stored so that 128-byte lines hold
+ * sets sharing a common subset; shorter rows keep colex order. `order` is host memory of n
+ * entries, n = C(k-1, m). CC_ERANGE for k outside [1, CC_MAX_K] or m outside [0, k-1], CC_EINVAL
+ * for a NULL pointer or another n.
+ */
+cc_status cc_entry_order(int32_t k, int32_t m, int32_t* order, int64_t n);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Load CSR graph                                                                               */
 /* ------------------------------------------------------------------------------------------ */

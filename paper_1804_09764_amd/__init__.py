@@ -15,6 +15,7 @@ Verbs (Section 2 "Subgraph-counting problem" and Algorithm 1 of the paper):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 from functools import lru_cache
@@ -71,7 +72,7 @@ class _Tuning(ctypes.Structure):
 
 
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
-           "cc_plan_bind_device", "cc_plan_destroy", "cc_graph_workspace_bytes", "cc_graph_prepare",
+           "cc_plan_bind_device", "cc_plan_destroy", "cc_entry_order", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
            "cc_multi_create", "cc_multi_info_get", "cc_multi_step_get", "cc_multi_destroy",
@@ -97,6 +98,7 @@ def lib() -> ctypes.CDLL:
                                              ctypes.POINTER(I32)]),
         "cc_plan_bind_device": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
         "cc_plan_destroy": (None, [P]),
+        "cc_entry_order": (ctypes.c_int, [I32, I32, P, I64]),
         "cc_graph_workspace_bytes": (ctypes.c_int, [I64, I64, P, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_graph_prepare": (ctypes.c_int, [I64, I64, P, P, P, ctypes.c_size_t, P, U32, P,
                                             ctypes.POINTER(P)]),
@@ -423,6 +425,15 @@ class Multi:
             except Exception:
                 pass
             self._h = None
+
+
+def entry_order(k: int, m: int) -> np.ndarray:
+    """Storage order of a table row of m-sets over the k-1 colours other than the anchor's:
+    element pos is the colex rank of the set stored at position pos (cc_entry_order)."""
+    n = math.comb(k - 1, m) if 0 <= m <= k - 1 else 0
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    _check(lib().cc_entry_order(k, m, out.ctypes.data, n))
+    return out[:n]
 
 
 def estimate(plan: Plan, X) -> tuple[float, float]:

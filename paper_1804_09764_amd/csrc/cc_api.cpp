@@ -313,6 +313,20 @@ cc_status cc_plan_bind_device(cc_plan* P, void* dev, size_t bytes, void* stream)
 
 void cc_plan_destroy(cc_plan* P) { delete P; }
 
+cc_status cc_entry_order(int32_t k, int32_t m, int32_t* order, int64_t n) {
+    if (k < 1 || k > cc::kMaxK) return fail(CC_ERANGE, "k out of range");
+    if (m < 0 || m > k - 1) return fail(CC_ERANGE, "m out of range");
+    if (!order) return fail(CC_EINVAL, "order is NULL");
+    if (n != cc::binom(k - 1, m)) return fail(CC_EINVAL, "n must be C(k-1, m)");
+    try {
+        const std::vector<int> o = cc::entry_order(k - 1, m);
+        for (int64_t i = 0; i < n; ++i) order[i] = o[(size_t)i];
+    } catch (const std::bad_alloc&) {
+        return fail(CC_ENOMEM, "host allocation failed");
+    }
+    return CC_OK;
+}
+
 cc_status cc_profile_enable(cc_plan* P, int32_t enable) {
     if (!P) return fail(CC_EINVAL, "NULL plan");
     for (auto& v : P->prof_events)

@@ -30,7 +30,8 @@ struct Split {
     int Wa, Wp, Ws; // anchored widths of T_i', T_i'', T_i
     int Nw;         // width of the neighbour sum N(v, Q), |Q| = p, Q over the k-1 other colours
     int npairs;     // C(s-1, p): splits of one output set
-    int64_t split_off;  // byte offset of the pair list in the device constants (-1 if a == 1)
+    int64_t split_off;  // byte offset of the pair list in the device constants (a = 1: N entry of
+                        // each output position)
     int64_t fold_off;   // byte offset of the fold map in the device constants (-1 if p == 1)
     int64_t mask_off;   // byte offset of the passive entries' colour-set masks (-1 if p == 1)
     // packed layout (several colourings per row): neighbour sums are kept over all k colours,
@@ -88,6 +89,9 @@ struct HubItem {
     int32_t n_chunks;
     int64_t first_chunk;
 };
+
+// storage order of a table row of m-sets over K colours: order[pos] = colex rank of the set at pos
+std::vector<int> entry_order(int K, int m);
 
 cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_plan* P,
                      std::string* err);

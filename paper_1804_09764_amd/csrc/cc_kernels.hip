@@ -316,8 +316,10 @@ __device__ __forceinline__ void combine_sets(const StepParams& S, double* orow, 
 __device__ void combine_store(const StepParams& S, int v, double* N, double* Ash, int lane) {
     double* orow = S.O + (int64_t)v * S.ostride;
     if (S.a == 1) {
-        // T' is the single vertex v: C(v, T', {col(v)}) = 1, so C(v, T, .) = N(v, .)
-        for (int r = lane; r < S.Ws; r += kWave) orow[r] = N[r];
+        // T' is the single vertex v: C(v, T', {col(v)}) = 1, so C(v, T, .) = N(v, .), written in
+        // the output row's storage order
+        // (with a = 1 the split list holds, for each output position, its entry of N)
+        for (int r = lane; r < S.Ws; r += kWave) orow[r] = N[S.split[r]];
         return;
     }
     const double* arow = S.A + (int64_t)v * S.astride;

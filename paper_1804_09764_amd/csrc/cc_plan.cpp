@@ -51,6 +51,45 @@ std::vector<uint32_t> masks_of(int K, int m) {
     return v;
 }
 
+// Storage order of the entries of a table row whose sets have m colours out of K: order[pos] =
+// colex rank of the set stored at position pos. Rows are read in 128-byte lines of 16 entries,
+// and a reader skips the entries whose set holds its own colour, so a line can be skipped only
+// when all of its sets share that colour. Lines are therefore filled, as far as possible, with
+// 16 sets that share a common subset Q (|Q| = 4, then 3, 2, 1): such a line is skipped for every
+// colour of Q. Sets left over keep colex order at the end. Rows of at most 16 entries keep colex
+// order.
+std::vector<int> table_order(int K, int m) {
+    const auto sets = masks_of(K, m);
+    const int W = (int)sets.size();
+    std::vector<int> order;
+    order.reserve((size_t)W);
+    if (W <= 16) {
+        for (int r = 0; r < W; ++r) order.push_back(r);
+        return order;
+    }
+    std::vector<char> used((size_t)W, 0);
+    for (int q = std::min(m, 4); q >= 1; --q)
+        for (uint32_t Q : masks_of(K, q)) {
+            std::vector<int> cand;
+            for (int r = 0; r < W; ++r)
+                if (!used[(size_t)r] && (sets[(size_t)r] & Q) == Q) cand.push_back(r);
+            const size_t full = cand.size() / 16 * 16;
+            for (size_t i = 0; i < full; ++i) {
+                order.push_back(cand[i]);
+                used[(size_t)cand[i]] = 1;
+            }
+        }
+    for (int r = 0; r < W; ++r)
+        if (!used[(size_t)r]) order.push_back(r);
+    return order;
+}
+
+std::vector<int> inverse(const std::vector<int>& order) {
+    std::vector<int> pos(order.size());
+    for (size_t i = 0; i < order.size(); ++i) pos[(size_t)order[i]] = (int)i;
+    return pos;
+}
+
 uint32_t expand_bits(uint32_t m, int c) {  // insert a zero bit at position c
     uint32_t lo = m & ((1u << c) - 1u);
     return lo | ((m >> c) << (c + 1));
@@ -368,6 +407,8 @@ Schedule share_tables(const Schedule& S) {
 
 }  // namespace
 
+std::vector<int> entry_order(int K, int m) { return table_order(K, m); }
+
 int64_t packed_arena(const cc_plan* P, int B, std::vector<int64_t>* col_off) {
     // the plan's allocation order: each split allocates its output table, then releases the
     // inputs it is the last reader of (a shared table has several readers)
@@ -484,9 +525,15 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
         sp.full_off = -1;
         sp.emap_off = -1;
         sp.Cf = (int)binom(k, sp.p);
+        // storage orders of the output, active and passive rows (tables of equal size share one)
+        const std::vector<int> order_s = table_order(K, sp.s - 1);
+        const std::vector<int> pos_s = inverse(order_s);
+        const std::vector<int> pos_a = inverse(table_order(K, sp.a - 1));
+        const std::vector<int> order_p = table_order(K, sp.p - 1);
         if (sp.a >= 2) {
-            // for every output set R (|R| = s-1, colex order) its p-subsets Q in increasing
-            // numeric order: (rank(R \ Q), rank(Q)) packed as lo16 | hi16 << 16, layout [j][r]
+            // for every output set R (|R| = s-1) its p-subsets Q in increasing numeric order:
+            // (storage position of R \ Q in the active row, colex rank of Q in N) packed as
+            // lo16 | hi16 << 16, layout [j][storage position of R in the output row]
             align();
             sp.split_off = (int64_t)C.size();
             auto outs = masks_of(K, sp.s - 1);
@@ -497,8 +544,8 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
                 uint32_t q = 0;
                 do {  // sub-masks of R in increasing numeric order
                     if (__builtin_popcount(q) == sp.p) {
-                        uint32_t ia = (uint32_t)colex_rank(R & ~q), in = (uint32_t)colex_rank(q);
-                        tab[(size_t)j * outs.size() + r] = ia | (in << 16);
+                        uint32_t ia = (uint32_t)pos_a[(size_t)colex_rank(R & ~q)], in = (uint32_t)colex_rank(q);
+                        tab[(size_t)j * outs.size() + (size_t)pos_s[r]] = ia | (in << 16);
                         ++j;
                     }
                     q = (q - R) & R;
@@ -513,7 +560,13 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
             // Q = R_u + {cu} written over the colours other than cv, unless cv is in R_u
             align();
             sp.fold_off = (int64_t)C.size();
-            auto rows = masks_of(K, sp.p - 1);
+            // passive rows in storage order: entry j holds the set of colex rank order_p[j]
+            std::vector<uint32_t> rows = masks_of(K, sp.p - 1);
+            {
+                std::vector<uint32_t> stored(rows.size());
+                for (size_t j = 0; j < rows.size(); ++j) stored[j] = rows[(size_t)order_p[j]];
+                rows.swap(stored);
+            }
             std::vector<uint16_t> tab((size_t)k * k * rows.size(), kNoSlot);
             for (int cu = 0; cu < k; ++cu)
                 for (int cv = 0; cv < k; ++cv) {
@@ -546,17 +599,29 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
             C.insert(C.end(), bf, bf + fm.size() * 2);
         }
         // packed layout: E[cv][q] = colex rank over all k colours of the p-set whose rank over the
-        // colours other than cv is q
+        // colours other than cv is q. With a = 1 the combine reads it by output position (the
+        // output set is that p-set plus cv), so q runs over the output row's storage order.
         {
             align();
             sp.emap_off = (int64_t)C.size();
             auto qs = masks_of(K, sp.p);
             std::vector<uint16_t> em((size_t)k * qs.size());
             for (int cv = 0; cv < k; ++cv)
-                for (size_t q = 0; q < qs.size(); ++q)
-                    em[(size_t)cv * qs.size() + q] = (uint16_t)colex_rank(expand_bits(qs[q], cv));
+                for (size_t q = 0; q < qs.size(); ++q) {
+                    const size_t qq = sp.a == 1 ? (size_t)order_s[q] : q;
+                    em[(size_t)cv * qs.size() + q] = (uint16_t)colex_rank(expand_bits(qs[qq], cv));
+                }
             const uint8_t* be = reinterpret_cast<const uint8_t*>(em.data());
             C.insert(C.end(), be, be + em.size() * 2);
+        }
+        // a = 1: the split list is the entry of N (colex rank) stored at each output position
+        if (sp.a == 1) {
+            align();
+            sp.split_off = (int64_t)C.size();
+            std::vector<uint32_t> om((size_t)sp.Ws);
+            for (int r = 0; r < sp.Ws; ++r) om[(size_t)r] = (uint32_t)order_s[(size_t)r];
+            const uint8_t* bo = reinterpret_cast<const uint8_t*>(om.data());
+            C.insert(C.end(), bo, bo + om.size() * 4);
         }
     }
     align();

@@ -167,6 +167,41 @@ def test_iterations_driver():
             cc.iterations(*bad)
 
 
+def _line_skips(sets, K):
+    """Lines of 16 entries that a reader anchored on colour x may skip (all sets hold x), summed
+    over the K colours x."""
+    return sum(all(sets[j] >> x & 1 for j in range(l, min(l + 16, len(sets))))
+               for x in range(K) for l in range(0, len(sets), 16))
+
+
+@pytest.mark.parametrize("k", [5, 8, 12, 16])
+def test_entry_order(k):
+    """Table rows are stored in a permutation of colex order; rows of at most 16 entries keep colex
+    order, and the grouped order lets readers skip at least as many 128-byte lines as colex."""
+    K = k - 1
+    for m in range(0, k):
+        o = cc.entry_order(k, m)
+        W = math.comb(K, m)
+        assert sorted(o.tolist()) == list(range(W))
+        if W <= 16:
+            assert o.tolist() == list(range(W))
+            continue
+        colex = [x for x in range(1 << K) if bin(x).count("1") == m]
+        stored = [colex[r] for r in o]
+        assert _line_skips(stored, K) >= _line_skips(colex, K)
+        if m >= 1 and math.comb(K - 1, m - 1) >= 16:
+            # 16 sets share a colour, so the first line is made of such sets
+            common = (1 << K) - 1
+            for x in stored[:16]:
+                common &= x
+            assert common != 0, (k, m)
+    for bad in ((0, 0), (17, 1), (5, -1), (5, 5)):
+        with pytest.raises(cc.CCError):
+            cc.entry_order(*bad)
+    with pytest.raises(cc.CCError):
+        cc._check(cc.lib().cc_entry_order(5, 2, None, 6))
+
+
 def test_epsilon_delta_estimate_on_brute_force():
     """Algorithm 1 end to end on the host: the driver's sample sizes, colourful counts of each
     colouring (oracle), the median of group means; the result is within epsilon of the number of
