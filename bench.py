@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 METRIC = "colour-set·edge updates/s (u12, RMAT-23) plain vs batched; p50/p99 latency"
 HBM_PEAK_GBPS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1804_09764_amd", "csrc", "cc_kernels.hip")
+PLAN_SRC = os.path.join(ROOT, "paper_1804_09764_amd", "csrc", "cc_plan.cpp")
 
 WORKLOADS = {
     # R-MAT (a, b, c) = (0.57, 0.19, 0.19), symmetrised, de-duplicated; 12-vertex Pruefer tree
@@ -45,7 +46,12 @@ DEFAULT_WORKLOAD = "rmat23-ef256-u12"
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of what fixes the split kernel's memory accesses: its source and the planner that
+    writes the table order, fold maps and masks it reads."""
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, PLAN_SRC):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def widths(k, s, a, p):

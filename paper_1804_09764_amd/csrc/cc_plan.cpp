@@ -79,9 +79,35 @@ std::vector<int> table_order(int K, int m) {
                 used[(size_t)cand[i]] = 1;
             }
         }
+    // chain the full lines so that neighbouring lines share as many common colours as possible:
+    // the lines a reader skips then sit together, and the lines it reads form fewer runs
+    const size_t nfull = order.size() / 16;
+    std::vector<uint32_t> common(nfull, (1u << K) - 1u);
+    for (size_t l = 0; l < nfull; ++l)
+        for (size_t i = 0; i < 16; ++i) common[l] &= sets[(size_t)order[l * 16 + i]];
+    std::vector<int> chain;
+    std::vector<char> taken(nfull, 0);
+    for (size_t step = 0; step < nfull; ++step) {
+        size_t best = nfull;
+        int best_shared = -1;
+        for (size_t l = 0; l < nfull; ++l) {
+            if (taken[l]) continue;
+            const int shared = chain.empty() ? 0 : __builtin_popcount(common[l] & common[(size_t)chain.back()]);
+            if (shared > best_shared) {
+                best_shared = shared;
+                best = l;
+            }
+        }
+        taken[best] = 1;
+        chain.push_back((int)best);
+    }
+    std::vector<int> chained;
+    chained.reserve((size_t)W);
+    for (int l : chain)
+        for (size_t i = 0; i < 16; ++i) chained.push_back(order[(size_t)l * 16 + i]);
     for (int r = 0; r < W; ++r)
-        if (!used[(size_t)r]) order.push_back(r);
-    return order;
+        if (!used[(size_t)r]) chained.push_back(r);
+    return chained;
 }
 
 std::vector<int> inverse(const std::vector<int>& order) {
