@@ -37,18 +37,33 @@ namespace cc {
 // is added. Consecutive members of one colour are summed in registers (in member order) and folded
 // into N through the fold map once per colour and block; the fold-map entries of a colour are
 // loaded together with the row of its first member. Fold-map entries and colour-set masks are
-// 16-bit, so each register holds those of two columns (t and t + 1): fewer registers per
-// wavefront, more wavefronts per SIMD, more rows in flight.
+// 16-bit; up to eight columns per lane each register holds those of two columns (t and t + 1):
+// fewer registers per wavefront, more wavefronts per SIMD, more rows in flight. At sixteen columns
+// the packed form was measured slower (two wavefronts per SIMD either way), so it keeps one per
+// register.
 template <int J>
-struct Half16 {
-    static constexpr int kWords = (J + 1) / 2;
+struct Idx16 {
+    static constexpr bool kPack = J <= 8;
+    static constexpr int kWords = kPack ? (J + 1) / 2 : J;
     uint32_t w[kWords];
-    __device__ __forceinline__ int get(int t) const { return (int)((w[t >> 1] >> (16 * (t & 1))) & 0xFFFFu); }
+    __device__ __forceinline__ int get(int t) const {
+        if constexpr (kPack) return (int)((w[t >> 1] >> (16 * (t & 1))) & 0xFFFFu);
+        else return (int)w[t];
+    }
+    // columns are put in increasing t; in the packed form an even t starts its register
+    __device__ __forceinline__ void put(int t, uint32_t v) {
+        if constexpr (kPack) w[t >> 1] = (t & 1) ? (w[t >> 1] | (v << 16)) : v;
+        else w[t] = v;
+    }
+    __device__ __forceinline__ void fill(uint32_t v) {
+#pragma unroll
+        for (int t = 0; t < J; ++t) put(t, v);
+    }
 };
 
 template <int J, int D>
 __device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, int su, int sc, int c0, int cv,
-                                           int lane, const Half16<J>& msk, double (&X)[D][J], Half16<J> (&F)[D]) {
+                                           int lane, const Idx16<J>& msk, double (&X)[D][J], Idx16<J> (&F)[D]) {
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         const int i = b * D + q;
@@ -61,19 +76,16 @@ __device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, 
             const double* row = S.P + (int64_t)ui * S.pstride + c0;
 #pragma unroll
             for (int t = 0; t < J; ++t) {
-                const bool need = ((msk.w[t >> 1] >> (16 * (t & 1) + x)) & 1u) == 0;
+                const bool need = ((msk.get(t) >> x) & 1) == 0;
                 X[q][t] = need ? row[lane + kWave * t] : 0.0;
             }
             const bool first = (i == 0) || (ci != bcast(sc, i > 0 ? i - 1 : 0));
             if (first) {
                 const uint16_t* fm = S.fold + ((int64_t)ci * S.k + cv) * S.Wp + c0;
 #pragma unroll
-                for (int h = 0; h < Half16<J>::kWords; ++h) {
-                    const int t0 = 2 * h, t1 = 2 * h + 1;
-                    const int j0 = c0 + lane + kWave * t0, j1 = c0 + lane + kWave * t1;
-                    const uint32_t lo = (j0 < S.Wp) ? (uint32_t)fm[lane + kWave * t0] : (uint32_t)kNoSlot;
-                    const uint32_t hi = (t1 < J && j1 < S.Wp) ? (uint32_t)fm[lane + kWave * t1] : (uint32_t)kNoSlot;
-                    F[q].w[h] = lo | (hi << 16);
+                for (int t = 0; t < J; ++t) {
+                    const int j = c0 + lane + kWave * t;
+                    F[q].put(t, (j < S.Wp) ? (uint32_t)fm[lane + kWave * t] : (uint32_t)kNoSlot);
                 }
             }
         }
@@ -81,7 +93,7 @@ __device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, 
 }
 
 template <int J>
-__device__ __forceinline__ void fold_acc(double* N, const double (&acc)[J], const Half16<J>& f) {
+__device__ __forceinline__ void fold_acc(double* N, const double (&acc)[J], const Idx16<J>& f) {
     // wide rows: one LDS add per entry (ds_add_f64, no read back; a wavefront's LDS operations
     // complete in issue order and one colour's targets are distinct, so each entry's order is
     // unchanged); narrow rows: read, add, write (measured faster there)
@@ -97,7 +109,7 @@ __device__ __forceinline__ void fold_acc(double* N, const double (&acc)[J], cons
 
 template <int J, int D>
 __device__ __forceinline__ void consume_batch(int b, int cnt, int sc, int& cur, double* N, double (&acc)[J],
-                                              Half16<J>& fcur, const double (&X)[D][J], const Half16<J> (&F)[D]) {
+                                              Idx16<J>& fcur, const double (&X)[D][J], const Idx16<J> (&F)[D]) {
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         const int i = b * D + q;
@@ -120,19 +132,16 @@ __device__ __forceinline__ void consume_batch(int b, int cnt, int sc, int& cur, 
 template <int J>
 __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
     constexpr int D = (J >= 6) ? 1 : (J >= 4) ? 2 : 4;  // rows per batch: two batches within the VGPR budget
-    constexpr uint32_t kNone = (uint32_t)kNoSlot | ((uint32_t)kNoSlot << 16);
     const int k = S.k;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
         // colour-set masks of this lane's columns; columns past the row get an all-ones mask,
         // which marks them as never needed
-        Half16<J> msk;
+        Idx16<J> msk;
 #pragma unroll
-        for (int h = 0; h < Half16<J>::kWords; ++h) {
-            const int j0 = c0 + lane + kWave * (2 * h), j1 = j0 + kWave;
-            const uint32_t lo = (j0 < S.Wp) ? (uint32_t)S.mask[j0] : 0xFFFFu;
-            const uint32_t hi = (2 * h + 1 < J && j1 < S.Wp) ? (uint32_t)S.mask[j1] : 0xFFFFu;
-            msk.w[h] = lo | (hi << 16);
+        for (int t = 0; t < J; ++t) {
+            const int j = c0 + lane + kWave * t;
+            msk.put(t, (j < S.Wp) ? (uint32_t)S.mask[j] : 0xFFFFu);
         }
         for (int64_t e0 = beg; e0 < end; e0 += kWave) {
             const int64_t e = e0 + lane;
@@ -153,16 +162,16 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
             const int su = __builtin_amdgcn_ds_permute(rank << 2, u);
             const int sc = __builtin_amdgcn_ds_permute(rank << 2, cu);
             double acc[J];
-            Half16<J> fcur;
+            Idx16<J> fcur;
             double XA[D][J], XB[D][J];
-            Half16<J> FA[D], FB[D];
+            Idx16<J> FA[D], FB[D];
 #pragma unroll
             for (int t = 0; t < J; ++t) acc[t] = 0.0;
+            fcur.fill(kNoSlot);
 #pragma unroll
-            for (int h = 0; h < Half16<J>::kWords; ++h) {
-                fcur.w[h] = kNone;
-#pragma unroll
-                for (int q = 0; q < D; ++q) FA[q].w[h] = FB[q].w[h] = kNone;
+            for (int q = 0; q < D; ++q) {
+                FA[q].fill(kNoSlot);
+                FB[q].fill(kNoSlot);
             }
             int cur = -1;
             const int nb = (cnt + D - 1) / D;
