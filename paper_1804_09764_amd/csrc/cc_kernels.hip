@@ -191,8 +191,8 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
 // Neighbour sum for narrow passive rows (Wp <= G <= 32): G lanes per row, so 64/G rows per load
 // instruction. The usable neighbours of a 64-entry block are sorted by colour as in gather_fold and
 // all of their rows are loaded at once and staged in LDS; each colour run is then summed column by
-// column in member order and folded into N, which is exactly gather_fold's arithmetic (same
-// order, same fold), so results do not depend on which of the two paths ran. Each lane keeps the
+// column in member order and folded into N in colour order, which is exactly gather_fold's
+// arithmetic (same order, same fold), so results do not depend on which of the two paths ran. Each lane keeps the
 // fold-map entries of its column for the colours of its slot (slot, slot + 64/G, ...).
 template <int G>
 __device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, double* stage,
@@ -242,21 +242,48 @@ __device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end
 #pragma unroll
         for (int q = 0; q < Q; ++q) stage[(q * R + g) * G + j] = x[q];
         wave_sync_lds();
+        // colour runs are taken R at a time, one per group of G lanes: each group sums its run in
+        // member order (four staged rows in flight), then the groups fold into N one after the
+        // other in run order, so every entry of N receives its terms in the order above
         int r0 = 0;
         while (r0 < cnt) {
-            const int c = bcast(sc, r0);
-            const int r1 = r0 + __popcll((unsigned long long)__ballot(lane < cnt && sc == c));
-            int f = (int)kNoSlot;
+            int my_s = 0, my_e = 0, idx = (int)kNoSlot;
 #pragma unroll
-            for (int m = 0; m < NC; ++m)
-                if (m == c / R) f = fidx[m];
-            const int idx = __shfl(f, (c % R) * G + j);
-            if (g == 0 && idx != (int)kNoSlot) {
-                double acc = stage[r0 * G + j];
-                for (int i = r0 + 1; i < r1; ++i) acc += stage[i * G + j];
-                N[idx] += acc;
+            for (int h = 0; h < R; ++h) {
+                const int c = r0 < cnt ? bcast(sc, r0) : -1;
+                const int r1 = c >= 0 ? r0 + __popcll((unsigned long long)__ballot(lane < cnt && sc == c)) : r0;
+                int f = (int)kNoSlot;
+#pragma unroll
+                for (int m = 0; m < NC; ++m)
+                    if (c >= 0 && m == c / R) f = fidx[m];
+                const int fh = __shfl(f, ((c >= 0 ? c : 0) % R) * G + j);
+                if (g == h) {
+                    my_s = r0;
+                    my_e = r1;
+                    idx = c >= 0 ? fh : (int)kNoSlot;
+                }
+                r0 = r1;
             }
-            r0 = r1;
+            const bool act = idx != (int)kNoSlot && my_s < my_e;
+            double acc = 0.0;
+            if (act) {
+                acc = stage[my_s * G + j];
+                int i = my_s + 1;
+                for (; i + 4 <= my_e; i += 4) {
+                    const double a0 = stage[i * G + j], a1 = stage[(i + 1) * G + j];
+                    const double a2 = stage[(i + 2) * G + j], a3 = stage[(i + 3) * G + j];
+                    acc += a0;
+                    acc += a1;
+                    acc += a2;
+                    acc += a3;
+                }
+                for (; i < my_e; ++i) acc += stage[i * G + j];
+            }
+#pragma unroll
+            for (int h = 0; h < R; ++h) {
+                if (g == h && act) N[idx] += acc;
+                wave_sync_lds();  // runs of different colours may reach the same entry
+            }
         }
         wave_sync_lds();
     }
