@@ -97,13 +97,14 @@ def needed_lines(k, p):
 
 def loaded_bytes(k, s, a, p, n, nnz):
     """Algorithmic bytes of one split launch: what its loads and stores must move from HBM at the
-    128-byte line granularity of the layout. Per CSR entry: the column (4 B), the neighbour's
-    colour (1 B) and, for the expected fraction (k-1)/k of neighbours whose colour differs from
-    the row's, the lines of the neighbour's colour-anchored passive row that hold an entry the row
-    needs (entries whose set holds the row's colour are skipped; none when p = 1); per vertex: its
-    row offsets, colour, active row (a >= 2) and output row."""
+    128-byte line granularity of the layout. Per CSR entry: the neighbour's colour (1 B, from the
+    per-entry colour array the count gathers once per colouring), the column (4 B, when p >= 2) and,
+    for the expected fraction (k-1)/k of neighbours whose colour differs from the row's, the lines
+    of the neighbour's colour-anchored passive row that hold an entry the row needs (entries whose
+    set holds the row's colour are skipped); per vertex: its row offsets, colour, active row
+    (a >= 2) and output row."""
     Wp, Wa, Ws = widths(k, s, a, p)
-    b = 5 * nnz + 8 * (n + 1) + n + 8 * n * Ws + (8 * n * Wa if a >= 2 else 0)
+    b = (5 if p >= 2 else 1) * nnz + 8 * (n + 1) + n + 8 * n * Ws + (8 * n * Wa if a >= 2 else 0)
     if p >= 2:
         b += 128 * needed_lines(k, p) * nnz * (k - 1) / k
     return b

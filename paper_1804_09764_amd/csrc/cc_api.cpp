@@ -61,7 +61,7 @@ GraphLayout graph_layout(int64_t n, int64_t nnz, int32_t thr, int32_t chunk) {
 }
 
 struct CountLayout {
-    size_t arena_off, partial_off, root_off, red_off, total;
+    size_t arena_off, partial_off, root_off, red_off, ecol_off, total;
     int64_t n_pad;
 };
 
@@ -72,7 +72,8 @@ CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
     L.partial_off = align256((size_t)P->arena_cols * (size_t)L.n_pad * sizeof(double));
     L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)P->max_stride_N * sizeof(double));
     L.red_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * sizeof(double));
-    L.total = align256(L.red_off + 1024 * sizeof(double));
+    L.ecol_off = align256(L.red_off + 1024 * sizeof(double));
+    L.total = align256(L.ecol_off + (size_t)std::max<int64_t>(G->nnz, 1));
     return L;
 }
 
@@ -108,6 +109,7 @@ cc::StepParams base_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     h.row_ptr = G->row_ptr;
     h.col = G->col;
     h.colour = colour;
+    h.ecol = nullptr;
     h.cstride = 1;
     h.light = G->light;
     h.light_start = G->light_start;
@@ -559,6 +561,7 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
     double* arena = (double*)(ws + L.arena_off);
     double* partial = (double*)(ws + L.partial_off);
     double* red = (double*)(ws + L.red_off);
+    uint8_t* ecol = ws + L.ecol_off;
     const int64_t n = G->n;
     hipError_t e = hipSuccess;
     for (int32_t b = 0; b < B; ++b) {
@@ -573,9 +576,13 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
             // k = 1: every vertex roots exactly one map
             e = cc::launch_fill_f64(root_out, n, 1.0, st);
         } else {
+            // every split reads the colour of each CSR entry's vertex: gathered once per
+            // colouring into a sequential array instead of once per split at random
+            e = cc::launch_edge_colours(G->col, colour, G->nnz, ecol, st);
             for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
                 const cc::Split& sp = P->splits[i];
                 cc::StepParams h = step_params(P, G, sp, colour, arena, L.n_pad, partial, root_out);
+                h.ecol = ecol;
                 hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
                 if (P->profiling) {
                     for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);

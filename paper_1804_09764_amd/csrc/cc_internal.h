@@ -121,6 +121,7 @@ struct StepParams {
     const int64_t* row_ptr;
     const int32_t* col;
     const uint8_t* colour;       // colour of vertex u at colour[u * cstride]
+    const uint8_t* ecol;         // NULL, or the colour of each CSR entry's vertex: ecol[e] = colour[col[e]]
     const int32_t* light;        // light rows, heaviest first
     const int32_t* light_start;  // light range r = light[light_start[r] .. light_start[r+1])
     const ChunkItem* chunks;
@@ -194,6 +195,8 @@ struct ReduceDesc {
 namespace cc {
 hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+// ecol[e] = colour[col[e]] for the nnz CSR entries (one colouring, colour stride 1)
+hipError_t launch_edge_colours(const int32_t* col, const uint8_t* colour, int64_t nnz, uint8_t* ecol, hipStream_t st);
 hipError_t launch_colour(uint64_t seed, uint64_t first_iter, int64_t n, int k, int B, uint8_t* out,
                          hipStream_t st);
 // root sums: blocks of kReducePerBlock values (at most 1024 blocks), then one final block; the

@@ -147,7 +147,7 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
             const int64_t e = e0 + lane;
             const bool valid = e < end;
             const int u = valid ? S.col[e] : 0;
-            const int cu = valid ? (int)S.colour[(int64_t)u * S.cstride] : 255;
+            const int cu = valid ? (int)(S.ecol ? S.ecol[e] : S.colour[(int64_t)u * S.cstride]) : 255;
             const bool use = valid && cu < k && cu != cv;
             const uint64_t used = __ballot(use);
             const int cnt = __popcll((unsigned long long)used);
@@ -216,7 +216,7 @@ __device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end
         const int64_t e = e0 + lane;
         const bool valid = e < end;
         const int u = valid ? S.col[e] : 0;
-        const int cu = valid ? (int)S.colour[(int64_t)u * S.cstride] : 255;
+        const int cu = valid ? (int)(S.ecol ? S.ecol[e] : S.colour[(int64_t)u * S.cstride]) : 255;
         const bool use = valid && cu < k && cu != cv;
         const uint64_t used = __ballot(use);
         const int cnt = __popcll((unsigned long long)used);
@@ -305,7 +305,7 @@ __device__ void count_colours(const StepParams& S, int64_t beg, int64_t end, int
     for (int64_t e0 = beg; e0 < end; e0 += kWave) {
         const int64_t e = e0 + lane;
         const bool valid = e < end;
-        const int cu = valid ? (int)S.colour[(int64_t)S.col[e] * S.cstride] : 255;
+        const int cu = valid ? (int)(S.ecol ? S.ecol[e] : S.colour[(int64_t)S.col[e] * S.cstride]) : 255;
         for (int c = 0; c < k; ++c) {
             const uint64_t b = __ballot(cu == c);
             if (c == my_c) cnt += (unsigned)__popcll((unsigned long long)b);
@@ -583,6 +583,21 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+// ecol[e] = colour[col[e]]: four CSR entries per thread when col is 16-byte aligned (ecol is)
+__global__ __launch_bounds__(256) void k_edge_colours(const int32_t* __restrict__ col, const uint8_t* __restrict__ colour,
+                                                      int64_t nnz, uint8_t* __restrict__ ecol, int vec) {
+    const int64_t quads = vec ? nnz / 4 : 0;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = t0; i < quads; i += step) {
+        const int4 c = reinterpret_cast<const int4*>(col)[i];
+        const uint32_t w = (uint32_t)colour[c.x] | ((uint32_t)colour[c.y] << 8) | ((uint32_t)colour[c.z] << 16) |
+                           ((uint32_t)colour[c.w] << 24);
+        reinterpret_cast<uint32_t*>(ecol)[i] = w;
+    }
+    for (int64_t e = quads * 4 + t0; e < nnz; e += step) ecol[e] = colour[col[e]];
+}
+
 // colours[b*n + v] = floor(k * h / 2^64), h = mix64(mix64(seed + G*(iter+1)) + H*(v+1))
 __global__ void k_colour(uint64_t seed, uint64_t first_iter, int64_t n, int k, int B, uint8_t* out) {
     const int64_t total = (int64_t)B * n;
@@ -678,6 +693,14 @@ hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st) {
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_colours(const int32_t* col, const uint8_t* colour, int64_t nnz, uint8_t* ecol, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    const int vec = ((uintptr_t)col % 16 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_edge_colours, dim3(grid_for(nnz / 4 + 1, 256, 65536)), dim3(256), 0, st, col, colour, nnz, ecol,
+                       vec);
     return hipGetLastError();
 }
 
