@@ -188,7 +188,9 @@ cc_status cc_color(const cc_graph* g, int32_t k, uint64_t seed, uint64_t first_i
 /* Count (Algorithm 1: the dynamic program of Eq. 1 over the partition, then Eq. 3's sum)      */
 /* ------------------------------------------------------------------------------------------ */
 
-/* Device workspace needed by cc_count for this plan on this graph (independent of B). */
+/* Device workspace needed by cc_count for this plan on this graph (independent of B): the live
+ * count tables, the cut rows' chunk partials, the root row, the reduction scratch and the
+ * per-CSR-entry neighbour colours of one colouring (nnz bytes). */
 cc_status cc_count_workspace_bytes(const cc_plan* plan, const cc_graph* g, size_t* bytes);
 
 /*
