@@ -240,6 +240,35 @@ def test_estimate_tracks_true_count(dev):
     assert abs(est - copies) < 5 * se
 
 
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_column_alignment_and_ragged_tail(dev, offset):
+    """The plain count gathers each CSR entry's neighbour colour once per colouring, four entries
+    per thread when the column array is 16-byte aligned and one per thread otherwise; nnz here is
+    2 mod 4, so the aligned path also runs its tail. Column views 0, 4 and 12 bytes past a 16-byte
+    boundary all equal the oracle."""
+    import torch
+    cc = _cc()
+    rp, cl = inputs.rmat_graph(10, 16, 9)
+    nnz = len(cl)
+    assert nnz % 4 == 2
+    big = torch.zeros(nnz + 8, dtype=torch.int32, device="cuda")
+    big[offset:offset + nnz] = torch.from_numpy(cl).cuda()
+    col_view = big[offset:offset + nnz]
+    assert col_view.data_ptr() % 16 == 4 * offset
+    G = cc.Graph(torch.from_numpy(rp).cuda(), col_view, hub_threshold=64, chunk=64)
+    k = 7
+    T = inputs.pruefer_tree(k, 4)
+    P = cc.Plan(T)
+    cols = np.stack([inputs.colours(len(rp) - 1, k, s) for s in (21, 22)])
+    X, V = cc.count(P, G, torch.from_numpy(cols).cuda(), per_vertex=True)
+    torch.cuda.synchronize()
+    for b in range(2):
+        print(f"case: column offset {offset} colouring {b}", flush=True)
+        Xo, Vo = oracle.count(rp, cl, cols[b], T, root=P.info.root, per_vertex=True)
+        assert_parity(V.cpu().numpy()[b], Vo)
+        assert_parity([float(X[b])], [Xo])
+
+
 def test_shared_and_unshared_plans_agree(dev):
     """A template with equal branches: the plan that runs each equal branch once and the plan that
     runs every split both match the oracle."""
