@@ -211,8 +211,16 @@ def bench(args):
           f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     T = inputs.pruefer_tree(W["k"], W["tseed"])
     k, B = W["k"], W["B"]
-    G = cc.Graph(rp_d, col_d, hub_threshold=args.hub_threshold, chunk=args.chunk, trust=W["trust"])
     P = cc.Plan(T)
+    tuned = None
+    if args.autotune:
+        # degree-split parameters by measurement (one colouring per candidate), before timing
+        from paper_1804_09764_amd import autotune
+        rec = autotune.tune(P, rp_d, col_d, seed=args.seed, cache_path=args.autotune, trust=W["trust"])
+        args.hub_threshold, args.chunk = rec.hub_threshold, rec.chunk
+        tuned = {"hub_threshold": rec.hub_threshold, "chunk": rec.chunk, "ms": rec.ms, "default_ms": rec.default_ms}
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
+    G = cc.Graph(rp_d, col_d, hub_threshold=args.hub_threshold, chunk=args.chunk, trust=W["trust"])
     units_per_edge = P.info.units_per_edge
     ws = cc.Workspace()
     colours = torch.empty((B, n), dtype=torch.uint8, device=dev)
@@ -296,7 +304,9 @@ def bench(args):
                    "template": f"Pruefer tree k={k} seed {W['tseed']}", "colourings_per_step": B,
                    "units_per_edge": units_per_edge, "path": "packed" if packed else "plain",
                    "colourings_per_packed_count": pack if packed else None,
-                   "workspace_GB": ws_bytes / 1e9},
+                   "workspace_GB": ws_bytes / 1e9,
+                   "degree_split": {"hub_threshold": G.info["hub_threshold"], "chunk": G.info["chunk"],
+                                    "autotuned": tuned}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
@@ -586,6 +596,9 @@ def main():
     ap.add_argument("--seed", type=int, default=777)
     ap.add_argument("--hub-threshold", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--autotune", default="", metavar="CACHE.json",
+                    help="pick the hub threshold and chunk size by timing candidates first (records "
+                         "cached in this JSON file)")
     ap.add_argument("--path", default="auto", choices=("auto", "packed", "plain"),
                     help="packed: the colourings of a step share the table rows (cc_count_packed); "
                          "plain: one colouring after another (cc_count); auto: packed when the step has "
