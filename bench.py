@@ -632,7 +632,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the counting path does not span GPUs "
-              "(sharding by colouring or by colour-set column is described in DESIGN.md).",
+              "(it would shard by colouring, or by colour-set column for a colouring too large "
+              "for one GPU; neither is built).",
               file=sys.stderr)
         return 2
     if args.copy_calibration:

@@ -19,7 +19,7 @@
  *   partition of the template in Figure 1(a)). The total over v at the full template is the number
  *   of colourful embeddings for one colouring (Algorithm 1, Eq. 3 before its k^k/k! scaling).
  *
- * Readings taken here (each listed in the design doc):
+ * Readings taken here, where the paper leaves a choice open:
  *   - The over-counting divisor d of Eq. 1 is not applied: the program counts labelled maps
  *     (injective homomorphisms phi : T -> G with col o phi injective), an exact integer. The
  *     estimate divides by |Aut(T)| once at the end.
