@@ -65,6 +65,20 @@ int main(void) {
     const double f = pow(5.0, 5.0) / 120.0 / 2.0;
     CHECK(fabs(est - 25.0 * f) <= 1e-12 * est, "estimate value %.17g", est);
 
+    /* storage order of table rows: a permutation of colex ranks; short rows keep colex order */
+    int32_t order[462];
+    int seen[462] = {0};
+    CHECK(cc_entry_order(12, 5, order, 462) == CC_OK, "entry order: %s", cc_last_error());
+    int perm = 1;
+    for (int i = 0; i < 462; ++i) {
+        if (order[i] < 0 || order[i] >= 462 || seen[order[i]]) perm = 0;
+        else seen[order[i]] = 1;
+    }
+    CHECK(perm, "entry order is a permutation");
+    CHECK(cc_entry_order(12, 1, order, 11) == CC_OK && order[0] == 0 && order[10] == 10, "short rows in colex order");
+    CHECK(cc_entry_order(12, 5, order, 461) == CC_EINVAL, "entry order size check");
+    CHECK(cc_entry_order(12, 12, order, 1) == CC_ERANGE, "entry order m range");
+
     cc_plan_destroy(p);
     cc_plan_destroy(q);
     cc_plan_destroy(r);
