@@ -222,6 +222,29 @@ def test_multi_template_count_shares_tables_and_matches(dev):
         assert_parity([Xh[t, 0], Xh[t, 4]], [oracle.count(rp, cl, cols[0], T), oracle.count(rp, cl, cols[4], T)])
 
 
+def test_multi_template_wide_rows(dev):
+    """Templates with 10 vertices, whose rows of more than 16 entries are stored in the grouped
+    order: the multi-template count equals each template's own packed count and the oracle."""
+    import torch
+    cc = _cc()
+    rp, cl = inputs.rmat_graph(8, 8, 5)
+    n = len(rp) - 1
+    G = cc.Graph.from_numpy(rp, cl, hub_threshold=64, chunk=64)
+    trees = [inputs.pruefer_tree(10, s) for s in (1, 2, 3)] + [inputs.path_tree(10), inputs.star_tree(10)]
+    plans = [cc.Plan(T) for T in trees]
+    M = cc.Multi(plans)
+    cols = oracle_colourings(n, 10, 3, 11)
+    C = torch.from_numpy(cols).cuda()
+    X = M.count(G, C)
+    single = [cc.count_packed(P, G, C) for P in plans]
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    for t, T in enumerate(trees):
+        print(f"case: multi-template wide rows, tree {t}", flush=True)
+        assert_parity(Xh[t], single[t].cpu().numpy())
+        assert_parity([Xh[t, 0], Xh[t, 2]], [oracle.count(rp, cl, cols[0], T), oracle.count(rp, cl, cols[2], T)])
+
+
 def test_multi_template_duplicates_roots_and_errors(dev):
     import torch
     cc = _cc()
