@@ -202,6 +202,22 @@ def test_entry_order(k):
         cc._check(cc.lib().cc_entry_order(5, 2, None, 6))
 
 
+def test_entry_order_line_counts():
+    """Expected 128-byte lines a reader fetches per row (bench.py's line model over the library's
+    order): 21.7 of 29 for the 462-entry rows of 12-vertex templates (25.4 in colex order), 17.5 of
+    21 for the 330-entry rows (19.2 in colex order)."""
+    import bench
+    assert abs(bench.needed_lines(12, 6) - 21.727) < 1e-3
+    assert abs(bench.needed_lines(12, 5) - 17.455) < 1e-3
+    K = 11
+    for p, colex_lines in ((6, 25.36), (5, 19.18)):
+        colex = [x for x in range(1 << K) if bin(x).count("1") == p - 1]
+        total = sum(any(not (colex[j] >> x) & 1 for j in range(l, min(l + 16, len(colex))))
+                    for x in range(K) for l in range(0, len(colex), 16))
+        assert abs(total / K - colex_lines) < 0.01
+        assert bench.needed_lines(12, p) < total / K
+
+
 def test_epsilon_delta_estimate_on_brute_force():
     """Algorithm 1 end to end on the host: the driver's sample sizes, colourful counts of each
     colouring (oracle), the median of group means; the result is within epsilon of the number of
