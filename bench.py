@@ -24,6 +24,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -45,12 +46,20 @@ WORKLOADS = {
 DEFAULT_WORKLOAD = "rmat23-ef256-u12"
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and blank lines (the sources hold no string literal with a
+    comment marker), so that edits to comments keep the hash."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_hash() -> str:
-    """Hash of what fixes the split kernel's memory accesses: its source and the planner that
-    writes the table order, fold maps and masks it reads."""
+    """Hash of what fixes the split kernel's memory accesses: its code and the planner's, which
+    writes the table order, fold maps and masks it reads (comments excluded)."""
     h = hashlib.sha256()
     for path in (KERNEL_SRC, PLAN_SRC):
-        h.update(open(path, "rb").read())
+        h.update(_code_only(open(path).read()).encode())
     return h.hexdigest()[:16]
 
 

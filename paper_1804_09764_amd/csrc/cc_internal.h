@@ -20,8 +20,9 @@ int64_t binom(int n, int r);
 // One cut of a sub-template T_i (size s) into the active part T_i' (size a, keeps the root) and
 // the passive part T_i'' (size p, rooted at the cut child). Table widths are per vertex, in the
 // colour-anchored layout: a table for a sub-template of size t stores, for vertex v, the counts of
-// the colour sets S with col(v) in S, indexed by the colex rank of S \ {col(v)} over the k-1
-// other colours (re-numbered 0..k-2). Its width is W(t) = C(k-1, t-1).
+// the colour sets S with col(v) in S, one entry per S \ {col(v)} over the k-1 other colours
+// (re-numbered 0..k-2), in the storage order entry_order gives for sets of t-1 colours (colex
+// order for rows of up to 16 entries). Its width is W(t) = C(k-1, t-1).
 struct Split {
     int s, a, p;
     int act;        // table id of T_i' (-1: a single vertex, count 1 for its own colour)

@@ -10,11 +10,14 @@
 //
 // Tables use the colour-anchored layout: a sub-template's count C(v, T_i, S) is zero unless
 // col(v) is in S (the root of T_i sits on v), so row v stores only the sets containing col(v),
-// indexed by the colex rank of S \ {col(v)} over the k-1 other colours renumbered 0..k-2. A
-// neighbour u's passive row is written over the colours other than col(u); the fold map
-// M[col(u)][col(v)][j] moves its entry j to the index of the same set over the colours other
-// than col(v) (or drops it when the set contains col(v), which no term of the combine can use).
-// Neighbours with col(u) = col(v) contribute nothing and are skipped.
+// one entry per set S \ {col(v)} over the k-1 other colours renumbered 0..k-2. Rows of up to 16
+// entries keep colex order; longer rows are stored with 128-byte lines of sets that share a
+// common subset (the planner's storage order), and the plan's maps are written for that order.
+// The neighbour sum N is indexed by colex rank. A neighbour u's passive row is written over the
+// colours other than col(u); the fold map M[col(u)][col(v)][j] moves its entry j to the index of
+// the same set over the colours other than col(v) (or drops it when the set contains col(v),
+// which no term of the combine can use). Neighbours with col(u) = col(v) contribute nothing and
+// are skipped.
 //
 // Work split (the neighbour-list partitioning of Section 3.3, Algorithm 4, on wavefronts): every
 // row of at most `hub_threshold` entries is one work item processed by one wavefront; longer rows
