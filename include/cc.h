@@ -109,6 +109,30 @@ cc_status cc_plan_info_get(const cc_plan* plan, cc_plan_info* out);
 /* Sub-template sizes of split i in execution order: *s = |T_i|, *a = |T_i'|, *p = |T_i''|. */
 cc_status cc_plan_split_get(const cc_plan* plan, int32_t i, int32_t* s, int32_t* a, int32_t* p);
 
+/* The maps one split reads (Section 2.1, Eq. 1: the neighbour sum over T_i'' and the combine over
+ * the splits of each colour set), as byte offsets into the plan's device constants (-1: absent):
+ *   split_off: a >= 2: u32 [C(s-1, p)][W(s)], for each output entry (storage order) its pairs
+ *              (storage position of S1 in the active row) | (colex rank of S \ S1 in N) << 16;
+ *              a = 1: u32 [W(s)], the colex rank in N of each output entry;
+ *   fold_off:  p >= 2: u16 [k][k][W(p)], fold[col(u)][col(v)][j] = colex rank in N of passive entry j,
+ *              or 0xFFFF when its set holds col(v);
+ *   mask_off:  p >= 2: u16 [W(p)], the colour set of passive entry j over the k-1 colours other
+ *              than the neighbour's;
+ *   full_off, emap_off: the packed layout's maps (colour sets over all k colours).
+ * act, pas: table ids read (-1: a single vertex); out: table id written (-2: the full template).
+ * For inspection and host-side checks of the planner; no count call needs it. CC_ERANGE for i out
+ * of range, CC_EINVAL for NULL arguments. */
+typedef struct {
+    int32_t act, pas, out;
+    int64_t split_off, fold_off, mask_off, full_off, emap_off;
+} cc_split_maps;
+
+cc_status cc_plan_split_maps(const cc_plan* plan, int32_t i, cc_split_maps* out);
+
+/* Copy the plan's device constants (info.device_bytes bytes) into host memory `host` of `bytes`
+ * bytes (CC_ENOSPC if smaller). Host-only; the same bytes cc_plan_bind_device uploads. */
+cc_status cc_plan_constants_get(const cc_plan* plan, void* host, size_t bytes);
+
 /*
  * Copy the plan's constant tables (colour-set split lists and neighbour fold maps) into the
  * caller's device buffer `dev` of at least info.device_bytes bytes, on `stream`, and remember it.

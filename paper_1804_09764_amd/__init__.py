@@ -47,6 +47,12 @@ class _PlanInfo(ctypes.Structure):
                 ("peak_live_columns", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
 
 
+class _SplitMaps(ctypes.Structure):
+    _fields_ = [("act", ctypes.c_int32), ("pas", ctypes.c_int32), ("out", ctypes.c_int32),
+                ("split_off", ctypes.c_int64), ("fold_off", ctypes.c_int64), ("mask_off", ctypes.c_int64),
+                ("full_off", ctypes.c_int64), ("emap_off", ctypes.c_int64)]
+
+
 class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("n_light", ctypes.c_int64), ("n_hubs", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
@@ -72,7 +78,8 @@ class _Tuning(ctypes.Structure):
 
 
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
-           "cc_plan_bind_device", "cc_plan_destroy", "cc_entry_order", "cc_graph_workspace_bytes", "cc_graph_prepare",
+           "cc_plan_bind_device", "cc_plan_destroy", "cc_entry_order", "cc_plan_split_maps",
+           "cc_plan_constants_get", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
            "cc_multi_create", "cc_multi_info_get", "cc_multi_step_get", "cc_multi_destroy",
@@ -99,6 +106,8 @@ def lib() -> ctypes.CDLL:
         "cc_plan_bind_device": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
         "cc_plan_destroy": (None, [P]),
         "cc_entry_order": (ctypes.c_int, [I32, I32, P, I64]),
+        "cc_plan_split_maps": (ctypes.c_int, [P, I32, ctypes.POINTER(_SplitMaps)]),
+        "cc_plan_constants_get": (ctypes.c_int, [P, P, ctypes.c_size_t]),
         "cc_graph_workspace_bytes": (ctypes.c_int, [I64, I64, P, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_graph_prepare": (ctypes.c_int, [I64, I64, P, P, P, ctypes.c_size_t, P, U32, P,
                                             ctypes.POINTER(P)]),
@@ -208,6 +217,18 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def split_maps(self, i: int) -> dict:
+        """Table ids and map offsets of split i in the plan's constants (cc_plan_split_maps)."""
+        m = _SplitMaps()
+        _check(lib().cc_plan_split_maps(self._h, i, ctypes.byref(m)))
+        return {f[0]: getattr(m, f[0]) for f in _SplitMaps._fields_}
+
+    def constants(self) -> np.ndarray:
+        """Host copy of the plan's device constants (uint8; cc_plan_constants_get)."""
+        out = np.zeros(max(self.info.device_bytes, 1), dtype=np.uint8)
+        _check(lib().cc_plan_constants_get(self._h, out.ctypes.data, out.nbytes))
+        return out[:self.info.device_bytes]
 
     def profile(self, enable: bool = True):
         """Record per-split kernel times of later counts with this plan (HIP events)."""

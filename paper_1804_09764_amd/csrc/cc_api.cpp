@@ -315,6 +315,28 @@ cc_status cc_plan_bind_device(cc_plan* P, void* dev, size_t bytes, void* stream)
 
 void cc_plan_destroy(cc_plan* P) { delete P; }
 
+cc_status cc_plan_split_maps(const cc_plan* P, int32_t i, cc_split_maps* o) {
+    if (!P || !o) return fail(CC_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int32_t)P->splits.size()) return fail(CC_ERANGE, "split index out of range");
+    const cc::Split& sp = P->splits[(size_t)i];
+    o->act = sp.act;
+    o->pas = sp.pas;
+    o->out = sp.out;
+    o->split_off = sp.split_off;
+    o->fold_off = sp.fold_off;
+    o->mask_off = sp.mask_off;
+    o->full_off = sp.full_off;
+    o->emap_off = sp.emap_off;
+    return CC_OK;
+}
+
+cc_status cc_plan_constants_get(const cc_plan* P, void* host, size_t bytes) {
+    if (!P || (!host && !P->consts.empty())) return fail(CC_EINVAL, "NULL argument");
+    if (bytes < P->consts.size()) return fail(CC_ENOSPC, "buffer smaller than the plan's constants");
+    if (!P->consts.empty()) std::memcpy(host, P->consts.data(), P->consts.size());
+    return CC_OK;
+}
+
 cc_status cc_entry_order(int32_t k, int32_t m, int32_t* order, int64_t n) {
     if (k < 1 || k > cc::kMaxK) return fail(CC_ERANGE, "k out of range");
     if (m < 0 || m > k - 1) return fail(CC_ERANGE, "m out of range");
