@@ -2,6 +2,7 @@
  * sizes and estimates. Built and run by tests/test_c_abi.py; prints one line per check. */
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "cc.h"
@@ -64,6 +65,21 @@ int main(void) {
     CHECK(cc_estimate(p, X, 4, &est, &se) == CC_OK, "estimate");
     const double f = pow(5.0, 5.0) / 120.0 / 2.0;
     CHECK(fabs(est - 25.0 * f) <= 1e-12 * est, "estimate value %.17g", est);
+
+    /* the planner's tables read back: offsets inside the constants, root split writes the full template */
+    cc_plan_info pi;
+    CHECK(cc_plan_info_get(p, &pi) == CC_OK, "plan info");
+    unsigned char* consts = (unsigned char*)malloc(pi.device_bytes ? pi.device_bytes : 1);
+    CHECK(consts != NULL && cc_plan_constants_get(p, consts, pi.device_bytes) == CC_OK, "constants");
+    CHECK(pi.device_bytes == 0 || cc_plan_constants_get(p, consts, pi.device_bytes - 1) == CC_ENOSPC, "constants size");
+    for (int32_t i = 0; i < pi.n_splits; ++i) {
+        cc_split_maps sm;
+        CHECK(cc_plan_split_maps(p, i, &sm) == CC_OK, "split maps %d", i);
+        CHECK(sm.split_off >= 0 && (size_t)sm.split_off < pi.device_bytes, "split list offset %d", i);
+        CHECK((sm.out == -2) == (i == pi.n_splits - 1), "root split writes the template %d", i);
+    }
+    CHECK(cc_plan_split_maps(p, pi.n_splits, NULL) == CC_EINVAL, "split maps NULL");
+    free(consts);
 
     /* storage order of table rows: a permutation of colex ranks; short rows keep colex order */
     int32_t order[462];
