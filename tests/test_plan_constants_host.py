@@ -3,8 +3,9 @@
 A plain evaluation of Eq. 1 (Section 2.1) in numpy that takes every map from the plan's device
 constants (split lists, output-to-N maps, fold maps, colour-set masks, in the tables' storage
 order) must equal the oracle exactly, per vertex. The masks must agree with the fold maps' drop
-rule, and the packed layout's maps must name the same colour sets as the fold maps. No GPU: these
-are the tables the kernels read, checked before any kernel runs.
+rule, the packed layout's maps must name the same colour sets as the fold maps, and the count
+through the packed maps (neighbour sums over all k colours) must equal the oracle too. No GPU:
+these are the tables the kernels read, checked before any kernel runs.
 """
 from math import comb
 
@@ -63,6 +64,48 @@ def host_count(P, rp, cl, col):
     raise AssertionError("no split writes the full template")
 
 
+def host_count_packed(P, rp, cl, col):
+    """The same count through the packed layout's maps: neighbour sums over all k colours
+    (C(k, p) entries, FM places passive entry j of a neighbour of colour c), entries whose set
+    holds col(v) skipped by the mask, and E reading them back per output entry."""
+    k = P.k
+    K = k - 1
+    C = P.constants()
+    n = len(rp) - 1
+    tables = {}
+    for i, (s, a, p) in enumerate(P.splits):
+        m = P.split_maps(i)
+        Wp, Ws, Nw, Cf = comb(K, p - 1), comb(K, s - 1), comb(K, p), comb(k, p)
+        E = _u16(C, m["emap_off"], k * Nw).reshape(k, Nw)
+        FM = _u16(C, m["full_off"], k * Wp).reshape(k, Wp) if p >= 2 else None
+        mask = _u16(C, m["mask_off"], Wp) if p >= 2 else None
+        Tp = tables[m["pas"]] if p >= 2 else None
+        Nf = np.zeros((n, Cf))
+        for v in range(n):
+            cv = int(col[v])
+            for u in cl[rp[v]:rp[v + 1]]:
+                c = int(col[u])
+                if c == cv:
+                    continue
+                if p == 1:
+                    Nf[v, c] += 1.0          # the full-space rank of {c} is c
+                else:
+                    need = ((mask >> (cv - (cv > c))) & 1) == 0
+                    np.add.at(Nf[v], FM[c][need], Tp[u][need])
+        Ev = E[np.asarray(col, dtype=np.int64)]                             # [n, Nw]: E[col(v)]
+        if a == 1:
+            O = Nf[np.arange(n)[:, None], Ev[:, :Ws]]
+        else:
+            npairs = comb(s - 1, p)
+            pairs = _u32(C, m["split_off"], npairs * Ws).reshape(npairs, Ws)
+            A = tables[m["act"]][:, pairs & 0xFFFF]                           # [n, npairs, Ws]
+            O = (A * Nf[np.arange(n)[:, None, None], Ev[:, pairs >> 16]]).sum(axis=1)
+        if m["out"] == -2:
+            return float(O[:, 0].sum()), O[:, 0]
+        tables[m["out"]] = O
+    raise AssertionError("no split writes the full template")
+
+
 CASES = [(k, T) for k in (2, 3, 5, 7) for T in inputs.all_trees(k)] + \
         [(k, T) for k in (9, 10, 11) for T in (inputs.path_tree(k), inputs.star_tree(k),
                                                 inputs.pruefer_tree(k, 1), inputs.pruefer_tree(k, 2))]
@@ -78,6 +121,18 @@ def test_constants_reproduce_oracle(flags):
         X, V = host_count(P, rp, cl, col)
         Xo, Vo = oracle.count(rp, cl, col, T, root=P.info.root, per_vertex=True)
         assert Xo < 2 ** 53
+        np.testing.assert_array_equal(V, Vo, err_msg=f"k={k} case {ci}")
+        assert X == Xo
+
+
+def test_packed_maps_reproduce_oracle():
+    rp, cl = inputs.er_graph(24, 80, 6)
+    n = len(rp) - 1
+    for ci, (k, T) in enumerate(CASES):
+        col = oracle.colour(200 + ci, 0, n, k)
+        P = cc.Plan(T, bind=False)
+        X, V = host_count_packed(P, rp, cl, col)
+        Xo, Vo = oracle.count(rp, cl, col, T, root=P.info.root, per_vertex=True)
         np.testing.assert_array_equal(V, Vo, err_msg=f"k={k} case {ci}")
         assert X == Xo
 
