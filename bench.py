@@ -35,7 +35,6 @@ if ROOT not in sys.path:
 METRIC = "colour-set·edge updates/s (u12, RMAT-23) plain vs batched; p50/p99 latency"
 HBM_PEAK_GBPS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1804_09764_amd", "csrc", "cc_kernels.hip")
-PLAN_SRC = os.path.join(ROOT, "paper_1804_09764_amd", "csrc", "cc_plan.cpp")
 
 WORKLOADS = {
     # R-MAT (a, b, c) = (0.57, 0.19, 0.19), symmetrised, de-duplicated; 12-vertex Pruefer tree
@@ -54,12 +53,15 @@ def _code_only(text: str) -> str:
     return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
 
 
-def kernel_hash() -> str:
-    """Hash of what fixes the split kernel's memory accesses: its code and the planner's, which
-    writes the table order, fold maps and masks it reads (comments excluded)."""
-    h = hashlib.sha256()
-    for path in (KERNEL_SRC, PLAN_SRC):
-        h.update(_code_only(open(path).read()).encode())
+def kernel_hash(workload: str = DEFAULT_WORKLOAD) -> str:
+    """Hash of what fixes the split kernel's memory accesses on a workload: the kernel's code
+    (comments excluded) and the device constants the planner writes for the workload's template
+    (row storage order, split lists, fold maps, masks), read back through cc_plan_constants_get."""
+    import inputs
+    import paper_1804_09764_amd as cc
+    W = WORKLOADS[workload]
+    h = hashlib.sha256(_code_only(open(KERNEL_SRC).read()).encode())
+    h.update(cc.Plan(inputs.pruefer_tree(W["k"], W["tseed"]), bind=False).constants().tobytes())
     return h.hexdigest()[:16]
 
 
@@ -146,7 +148,7 @@ def load_traffic(workload: str, split_index: int):
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_hash") != kernel_hash() or d.get("split_index") != split_index:
+    if d.get("kernel_hash") != kernel_hash(workload) or d.get("split_index") != split_index:
         return None
     return d["traffic_bytes_per_launch"] / 1e9
 
@@ -586,7 +588,7 @@ def summarize_pmc(args):
     wsel = [wsplit[i] for i in range(idx, len(wsplit), nspl)]
     fetch_kib = sum(fsel) / len(fsel)
     write_kib = sum(wsel) / len(wsel)
-    res = {"workload": args.workload, "kernel_hash": kernel_hash(), "split_index": idx,
+    res = {"workload": args.workload, "kernel_hash": kernel_hash(args.workload), "split_index": idx,
            "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
            "copy_fetch_factor": f_factor, "copy_write_factor": w_factor,
            "traffic_bytes_per_launch": fetch_kib * 1024.0 * f_factor + write_kib * 1024.0 * w_factor,

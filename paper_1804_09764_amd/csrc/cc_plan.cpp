@@ -35,20 +35,43 @@ int pad_stride(int W) {
 
 namespace {
 
-// colex rank over K colours: rank({c_0 < c_1 < ...}) = sum_j C(c_j, j+1)
+// colex rank: rank({c_0 < c_1 < ...}) = sum_j C(c_j, j+1), the same over any number of colours.
+// Tabulated once for every mask of up to 16 colours: removing the largest element c of a set of
+// j elements lowers its rank by C(c, j).
 int colex_rank(uint32_t mask) {
-    int r = 0, j = 0;
-    for (int c = 0; mask; ++c, mask >>= 1)
-        if (mask & 1u) r += (int)binom(c, ++j);
-    return r;
+    static const std::vector<int> table = [] {
+        int B[17][17];
+        for (int n = 0; n <= 16; ++n)
+            for (int r = 0; r <= 16; ++r) B[n][r] = (int)binom(n, r);
+        std::vector<int> t(1u << 16, 0);
+        for (uint32_t m = 1; m < (1u << 16); ++m) {
+            const int c = 31 - __builtin_clz(m);
+            t[m] = t[m ^ (1u << c)] + B[c][__builtin_popcount(m)];
+        }
+        return t;
+    }();
+    return table[mask];
 }
 
-// all masks of popcount m over K bits, in colex (= increasing numeric) order
 std::vector<uint32_t> masks_of(int K, int m) {
     std::vector<uint32_t> v;
     for (uint32_t x = 0; x < (1u << K); ++x)
         if (__builtin_popcount(x) == m) v.push_back(x);
     return v;
+}
+
+// the low bits of x placed on the set bits of R, lowest first: increasing in x
+uint32_t deposit(uint32_t x, uint32_t R) {
+    uint32_t out = 0;
+    for (uint32_t b = 1; R != 0; R &= R - 1, b <<= 1)
+        if (x & b) out |= R & (~R + 1u);
+    return out;
+}
+
+// the next larger integer with as many set bits as x
+uint32_t next_same_popcount(uint32_t x) {
+    const uint32_t c = x & (~x + 1u), r = x + c;
+    return (((r ^ x) >> 2) / c) | r;
 }
 
 // Storage order of the entries of a table row whose sets have m colours out of K: order[pos] =
@@ -70,9 +93,19 @@ std::vector<int> table_order(int K, int m) {
     std::vector<char> used((size_t)W, 0);
     for (int q = std::min(m, 4); q >= 1; --q)
         for (uint32_t Q : masks_of(K, q)) {
+            // the unused supersets of Q in colex order: Q plus the (m-q)-subsets of the other
+            // colours, in increasing numeric order
             std::vector<int> cand;
-            for (int r = 0; r < W; ++r)
-                if (!used[(size_t)r] && (sets[(size_t)r] & Q) == Q) cand.push_back(r);
+            const uint32_t rest = ((1u << K) - 1u) & ~Q;
+            if (m == q) {
+                const int r = colex_rank(Q);
+                if (!used[(size_t)r]) cand.push_back(r);
+            } else {
+                for (uint32_t x = (1u << (m - q)) - 1u; x < (1u << (K - q)); x = next_same_popcount(x)) {
+                    const int r = colex_rank(Q | deposit(x, rest));
+                    if (!used[(size_t)r]) cand.push_back(r);
+                }
+            }
             const size_t full = cand.size() / 16 * 16;
             for (size_t i = 0; i < full; ++i) {
                 order.push_back(cand[i]);
@@ -544,6 +577,11 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
     std::vector<uint8_t>& C = P->consts;
     C.clear();
     auto align = [&]() { while (C.size() % 256) C.push_back(0); };
+    std::vector<std::vector<int>> orders((size_t)k);  // storage order per set size, built once
+    auto order_of = [&](int m) -> const std::vector<int>& {
+        if (orders[(size_t)m].empty()) orders[(size_t)m] = table_order(K, m);
+        return orders[(size_t)m];
+    };
     for (auto& sp : P->splits) {
         sp.split_off = -1;
         sp.fold_off = -1;
@@ -552,10 +590,10 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
         sp.emap_off = -1;
         sp.Cf = (int)binom(k, sp.p);
         // storage orders of the output, active and passive rows (tables of equal size share one)
-        const std::vector<int> order_s = table_order(K, sp.s - 1);
+        const std::vector<int>& order_s = order_of(sp.s - 1);
         const std::vector<int> pos_s = inverse(order_s);
-        const std::vector<int> pos_a = inverse(table_order(K, sp.a - 1));
-        const std::vector<int> order_p = table_order(K, sp.p - 1);
+        const std::vector<int> pos_a = inverse(order_of(sp.a - 1));
+        const std::vector<int>& order_p = order_of(sp.p - 1);
         if (sp.a >= 2) {
             // for every output set R (|R| = s-1) its p-subsets Q in increasing numeric order:
             // (storage position of R \ Q in the active row, colex rank of Q in N) packed as
@@ -565,17 +603,17 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
             auto outs = masks_of(K, sp.s - 1);
             std::vector<uint32_t> tab((size_t)sp.npairs * outs.size());
             for (size_t r = 0; r < outs.size(); ++r) {
-                uint32_t R = outs[r];
+                const uint32_t R = outs[r];
+                const uint32_t end = 1u << (sp.s - 1);  // |R| = s - 1
                 int j = 0;
-                uint32_t q = 0;
-                do {  // sub-masks of R in increasing numeric order
-                    if (__builtin_popcount(q) == sp.p) {
-                        uint32_t ia = (uint32_t)pos_a[(size_t)colex_rank(R & ~q)], in = (uint32_t)colex_rank(q);
-                        tab[(size_t)j * outs.size() + (size_t)pos_s[r]] = ia | (in << 16);
-                        ++j;
-                    }
-                    q = (q - R) & R;
-                } while (q != 0);
+                // the p-subsets of R in increasing numeric order: the p-bit patterns over R's bits
+                // in increasing order, deposited on them
+                for (uint32_t x = (1u << sp.p) - 1u; x < end; x = next_same_popcount(x)) {
+                    const uint32_t q = deposit(x, R);
+                    const uint32_t ia = (uint32_t)pos_a[(size_t)colex_rank(R & ~q)], in = (uint32_t)colex_rank(q);
+                    tab[(size_t)j * outs.size() + (size_t)pos_s[r]] = ia | (in << 16);
+                    ++j;
+                }
             }
             const uint8_t* b = reinterpret_cast<const uint8_t*>(tab.data());
             C.insert(C.end(), b, b + tab.size() * 4);
