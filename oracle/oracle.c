@@ -140,10 +140,12 @@ int orc_step(int k, int s, int a, int64_t nv, const int64_t* nbr_ptr, const int3
         }
     }
     if (threads > 0) omp_set_num_threads(threads);
-#pragma omp parallel for schedule(dynamic, 16)
+    /* every (centre, colour set) entry is one independent task: a single high-degree centre is
+       spread over the threads, and each entry's sum is accumulated in the same order as ever */
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
     for (int64_t i = 0; i < nv; ++i) {
-        const double* arow = act + i * wa;
         for (int64_t r = 0; r < ws; ++r) {
+            const double* arow = act + i * wa;
             long double sum = 0.0L, comp = 0.0L;
             for (int64_t e = nbr_ptr[i]; e < nbr_ptr[i + 1]; ++e) {
                 const double* prow = pas + (int64_t)nbr[e] * wp;
