@@ -106,6 +106,32 @@ def needed_lines(k, p):
     return total / K
 
 
+def method_bytes(k, s, a, p, n, nnz):
+    """Bytes the method must move for one split launch, counting only the values the arithmetic
+    uses. Per CSR entry: the neighbour's colour (1 B, from the per-entry colour array the count
+    gathers once per colouring), the column (4 B, when p >= 2) and, for the expected fraction
+    (k-1)/k of neighbours whose colour differs from the row's, the C(k-2, p-1) entries of the
+    neighbour's colour-anchored passive row whose set avoids the row's colour (8 B each; the
+    other entries of that row add to sets no term of the combine reads). Per vertex: its row
+    offsets, colour, active row (a >= 2) and output row."""
+    Wp, Wa, Ws = widths(k, s, a, p)
+    b = (5 if p >= 2 else 1) * nnz + 8 * (n + 1) + n + 8 * n * Ws + (8 * n * Wa if a >= 2 else 0)
+    if p >= 2:
+        b += 8 * math.comb(k - 2, p - 1) * nnz * (k - 1) / k
+    return b
+
+
+def method_bytes_packed(k, s, a, p, n, nnz, B):
+    """method_bytes for a packed launch of B colourings: per CSR entry the column, the neighbour's
+    B colours and the needed passive entries of each colouring; per vertex B colours, B active rows
+    (a >= 2) and B output rows."""
+    Wp, Wa, Ws = widths(k, s, a, p)
+    b = (4 + B) * nnz + 8 * (n + 1) + B * n + 8 * B * n * Ws + (8 * B * n * Wa if a >= 2 else 0)
+    if p >= 2:
+        b += 8 * B * math.comb(k - 2, p - 1) * nnz * (k - 1) / k
+    return b
+
+
 def loaded_bytes(k, s, a, p, n, nnz):
     """Algorithmic bytes of one split launch: what its loads and stores must move from HBM at the
     128-byte line granularity of the layout. Per CSR entry: the neighbour's colour (1 B, from the
@@ -291,7 +317,8 @@ def bench(args):
     s, a, p = P.splits[dom]
     avg_ms = gather_ms[dom] / max(1, launches[dom])
     dom_packed = packed and packed_kernel_split(k, s, a, p)
-    alg = loaded_bytes_packed(k, s, a, p, n, nnz, pack) if dom_packed else loaded_bytes(k, s, a, p, n, nnz)
+    alg = method_bytes_packed(k, s, a, p, n, nnz, pack) if dom_packed else method_bytes(k, s, a, p, n, nnz)
+    lines = loaded_bytes_packed(k, s, a, p, n, nnz, pack) if dom_packed else loaded_bytes(k, s, a, p, n, nnz)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     traffic = None if dom_packed else load_traffic(args.workload, dom)
     per_split = [{"s": S, "a": A, "p": Pp, "gather_ms": round(float(g) / max(1, c), 4),
@@ -321,12 +348,21 @@ def bench(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_unit": "GB per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by what they "
+                                     "read for a 1 GiB device copy. These count L2-to-fabric requests, "
+                                     "Infinity Cache hits included: an upper bound of the DRAM bytes, not "
+                                     "a DRAM measurement",
                      "kernel": f"{'k_psplit' if dom_packed else 'k_split'} split {dom} (s={s}, a={a}, p={p})",
                      "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg,
+                     "algorithmic_bytes": "method bytes: only the passive entries the combine uses "
+                                          "(bench.py method_bytes)",
+                     "line_bytes_per_launch": lines,
+                     "line_GBps": lines / (avg_ms * 1e-3) / 1e9,
+                     "line_bytes": "the 128-byte lines holding a needed entry (bench.py loaded_bytes)",
                      "compulsory_bytes_per_launch": split_bytes(k, s, a, p, n, nnz),
-                     "traffic_GBps": (traffic / (avg_ms * 1e-3)) if traffic else None},
+                     "traffic_GBps": (traffic / (avg_ms * 1e-3)) if traffic else None,
+                     "traffic_over_method": (traffic * 1e9 / alg) if traffic else None},
         "splits": per_split,
         "X_last": [float(x) for x in Xh],
     }

@@ -228,6 +228,37 @@ cc_status cc_count_workspace_bytes(const cc_plan* plan, const cc_graph* g, size_
 cc_status cc_count(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
                    void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
 
+/*
+ * Inspection of one step of the dynamic program (Section 2.1, Eq. 1: the table C(., T_i, .) of a
+ * split is computed from the tables of its active part T_i' and passive part T_i'' alone), so that
+ * a caller can check any single split at sizes where the whole count cannot be recomputed on the
+ * host. Runs the splits 0..last (execution order) of one colouring (colours_dev: n bytes) in the
+ * count workspace of cc_count (ws_bytes >= cc_count_workspace_bytes) and stops, without the root
+ * reduction. Afterwards the tables that split `last` reads (its act and pas ids from
+ * cc_plan_split_maps) and the table it writes (its out id) hold their values in the workspace
+ * (cc_plan_table_get says where); when split `last` is the root split (out = -2) its per-vertex
+ * counts go to vertex_dev (n doubles, required then, ignored otherwise). Queued on `stream`.
+ * CC_ERANGE for `last` out of range, CC_EINVAL for NULL pointers or an unbound plan, CC_ENOSPC
+ * for a small workspace.
+ */
+cc_status cc_count_inspect(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t last,
+                           void* ws_dev, size_t ws_bytes, double* vertex_dev, void* stream);
+
+/* Where table `table` (an id of cc_plan_split_maps) lives in a cc_count workspace for this plan on
+ * this graph: row v of the table starts at byte offset + 8 * v * stride of the workspace and holds
+ * width = C(k-1, size-1) doubles, the counts C(v, T_i, S) of the colour sets S of `size` colours
+ * that contain col(v); entry j is the set made of col(v) and the (size-1)-set over the other k-1
+ * colours (renumbered 0..k-2 in increasing order) whose colex rank is order[j] of
+ * cc_entry_order(k, size-1). Host-only. CC_ERANGE for a table id out of range. */
+typedef struct {
+    int32_t size;    /* sub-template size |T_i| */
+    int32_t width;   /* doubles per row that hold counts */
+    int64_t stride;  /* doubles between the rows of consecutive vertices */
+    int64_t offset;  /* byte offset of vertex 0's row in the workspace */
+} cc_table_desc;
+
+cc_status cc_plan_table_get(const cc_plan* plan, const cc_graph* g, int32_t table, cc_table_desc* out);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Packed count: B colourings of one template in one pass over the graph                        */
 /* ------------------------------------------------------------------------------------------ */

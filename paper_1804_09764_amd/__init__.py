@@ -53,6 +53,11 @@ class _SplitMaps(ctypes.Structure):
                 ("full_off", ctypes.c_int64), ("emap_off", ctypes.c_int64)]
 
 
+class _TableDesc(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("width", ctypes.c_int32), ("stride", ctypes.c_int64),
+                ("offset", ctypes.c_int64)]
+
+
 class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("n_light", ctypes.c_int64), ("n_hubs", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
@@ -81,6 +86,7 @@ EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split
            "cc_plan_bind_device", "cc_plan_destroy", "cc_entry_order", "cc_plan_split_maps",
            "cc_plan_constants_get", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
+           "cc_count_inspect", "cc_plan_table_get",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
            "cc_multi_create", "cc_multi_info_get", "cc_multi_step_get", "cc_multi_destroy",
            "cc_count_packed_multi_workspace_bytes",
@@ -116,6 +122,8 @@ def lib() -> ctypes.CDLL:
         "cc_color": (ctypes.c_int, [P, I32, U64, U64, I32, P, P]),
         "cc_count_workspace_bytes": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
+        "cc_count_inspect": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P]),
+        "cc_plan_table_get": (ctypes.c_int, [P, P, I32, ctypes.POINTER(_TableDesc)]),
         "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_stream_check": (ctypes.c_int, [P]),
@@ -350,6 +358,45 @@ def count(plan: Plan, graph: Graph, colours, per_vertex: bool = False, workspace
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dev_ptr(X, torch.float64, "X"),
                           _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
     return (X, V) if per_vertex else X
+
+
+def count_inspect(plan: Plan, graph: Graph, colours, last: int, workspace: Workspace | None = None,
+                  vertex_out=None, stream=None):
+    """Run the splits 0..last of one colouring (`colours`: n uint8 on the GPU) and stop
+    (cc_count_inspect). Returns the workspace tensor (uint8) that holds the tables, and the
+    per-vertex root counts (float64, n) when split `last` is the root split, else None."""
+    import torch
+    colours = colours.reshape(-1)
+    if colours.numel() != graph.n:
+        raise ValueError("colours must have n entries")
+    dev = graph.row_ptr.device
+    ws = (workspace or Workspace()).get(count_workspace_bytes(plan, graph), dev)
+    V = None
+    if plan.split_maps(last)["out"] == -2:
+        V = vertex_out if vertex_out is not None else torch.empty(graph.n, dtype=torch.float64, device=dev)
+    _check(lib().cc_count_inspect(plan.handle, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), last,
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                  _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
+    return ws, V
+
+
+def table_desc(plan: Plan, graph: Graph, table: int) -> dict:
+    """Where table `table` lives in a count workspace (cc_plan_table_get): size, width, stride
+    (doubles between rows), offset (bytes)."""
+    d = _TableDesc()
+    _check(lib().cc_plan_table_get(plan.handle, graph.handle, table, ctypes.byref(d)))
+    return {f[0]: getattr(d, f[0]) for f in _TableDesc._fields_}
+
+
+def table_rows(ws, desc: dict, vertices):
+    """Rows of the given vertices of a table in a count workspace, as a float64 GPU tensor
+    [len(vertices), width] (a gather over the caller's workspace tensor; no kernel of the library)."""
+    import torch
+    nbytes = ws.numel() - desc["offset"]
+    flat = ws[desc["offset"]:desc["offset"] + nbytes // 8 * 8].view(torch.float64)
+    idx = torch.as_tensor(vertices, dtype=torch.int64, device=ws.device)
+    base = (idx * desc["stride"]).unsqueeze(1) + torch.arange(desc["width"], device=ws.device).unsqueeze(0)
+    return flat[base]
 
 
 def count_packed_workspace_bytes(plan: Plan, graph: Graph, B: int) -> int:

@@ -569,6 +569,42 @@ cc_status cc_count_workspace_bytes(const cc_plan* P, const cc_graph* G, size_t* 
     return CC_OK;
 }
 
+namespace {
+
+// Splits [0, last] of plan P for one colouring on `st`: the per-entry neighbour colours, then
+// every split's gather + combine and cut-row finish, timed per split while profiling.
+hipError_t run_splits(const cc_plan* P, const cc_graph* G, const uint8_t* colour, const CountLayout& L, uint8_t* ws,
+                      double* root_out, int64_t last, hipStream_t st) {
+    double* arena = (double*)(ws + L.arena_off);
+    double* partial = (double*)(ws + L.partial_off);
+    uint8_t* ecol = ws + L.ecol_off;
+    // every split reads the colour of each CSR entry's vertex: gathered once per colouring into a
+    // sequential array instead of once per split at random
+    hipError_t e = cc::launch_edge_colours(G->col, colour, G->nnz, ecol, st);
+    for (int64_t i = 0; e == hipSuccess && i <= last; ++i) {
+        const cc::Split& sp = P->splits[(size_t)i];
+        cc::StepParams h = step_params(P, G, sp, colour, arena, L.n_pad, partial, root_out);
+        h.ecol = ecol;
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        if (P->profiling) {
+            for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+            if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+        }
+        if (e == hipSuccess) e = cc::launch_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
+        if (e == hipSuccess && P->profiling) {
+            e = hipEventRecord(ev[2], st);
+            auto& pe = P->prof_events[(size_t)i];
+            pe.push_back(ev[0]);
+            pe.push_back(ev[1]);
+            pe.push_back(ev[2]);
+            P->prof_launches[(size_t)i] += 1;
+        }
+    }
+    return e;
+}
+
+}  // namespace
+
 cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_dev, int32_t B, void* ws_dev,
                    size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream) {
     if (!P || !G) return fail(CC_EINVAL, "NULL plan or graph");
@@ -580,10 +616,7 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
     if (ws_bytes < L.total) return fail(CC_ENOSPC, "count workspace too small");
     hipStream_t st = (hipStream_t)stream;
     uint8_t* ws = (uint8_t*)ws_dev;
-    double* arena = (double*)(ws + L.arena_off);
-    double* partial = (double*)(ws + L.partial_off);
     double* red = (double*)(ws + L.red_off);
-    uint8_t* ecol = ws + L.ecol_off;
     const int64_t n = G->n;
     hipError_t e = hipSuccess;
     for (int32_t b = 0; b < B; ++b) {
@@ -598,32 +631,39 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
             // k = 1: every vertex roots exactly one map
             e = cc::launch_fill_f64(root_out, n, 1.0, st);
         } else {
-            // every split reads the colour of each CSR entry's vertex: gathered once per
-            // colouring into a sequential array instead of once per split at random
-            e = cc::launch_edge_colours(G->col, colour, G->nnz, ecol, st);
-            for (size_t i = 0; e == hipSuccess && i < P->splits.size(); ++i) {
-                const cc::Split& sp = P->splits[i];
-                cc::StepParams h = step_params(P, G, sp, colour, arena, L.n_pad, partial, root_out);
-                h.ecol = ecol;
-                hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-                if (P->profiling) {
-                    for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
-                    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-                }
-                if (e == hipSuccess) e = cc::launch_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
-                if (e == hipSuccess && P->profiling) {
-                    e = hipEventRecord(ev[2], st);
-                    auto& pe = P->prof_events[i];
-                    pe.push_back(ev[0]);
-                    pe.push_back(ev[1]);
-                    pe.push_back(ev[2]);
-                    P->prof_launches[i] += 1;
-                }
-            }
+            e = run_splits(P, G, colour, L, ws, root_out, (int64_t)P->splits.size() - 1, st);
         }
         if (e == hipSuccess) e = cc::launch_reduce(root_out, n, red, X_dev + b, st);
         if (e != hipSuccess) return hip_fail(e, "count launch");
     }
+    return CC_OK;
+}
+
+cc_status cc_count_inspect(const cc_plan* P, const cc_graph* G, const uint8_t* colours_dev, int32_t last,
+                           void* ws_dev, size_t ws_bytes, double* vertex_dev, void* stream) {
+    if (!P || !G) return fail(CC_EINVAL, "NULL plan or graph");
+    if (last < 0 || last >= (int32_t)P->splits.size()) return fail(CC_ERANGE, "split index out of range");
+    if (!ws_dev || (G->n > 0 && !colours_dev)) return fail(CC_EINVAL, "NULL buffer");
+    if (P->splits[(size_t)last].out == -2 && !vertex_dev && G->n > 0)
+        return fail(CC_EINVAL, "the last split writes the root counts: vertex_dev is needed");
+    if (!P->dev) return fail(CC_EINVAL, "plan not bound to device memory");
+    CountLayout L = count_layout(P, G);
+    if (ws_bytes < L.total) return fail(CC_ENOSPC, "count workspace too small");
+    if (G->n == 0) return CC_OK;
+    hipError_t e = run_splits(P, G, colours_dev, L, (uint8_t*)ws_dev, vertex_dev, last, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "inspection count launch");
+    return CC_OK;
+}
+
+cc_status cc_plan_table_get(const cc_plan* P, const cc_graph* G, int32_t table, cc_table_desc* o) {
+    if (!P || !G || !o) return fail(CC_EINVAL, "NULL argument");
+    if (table < 0 || table >= (int32_t)P->tables.size()) return fail(CC_ERANGE, "table id out of range");
+    const cc::Table& t = P->tables[(size_t)table];
+    const CountLayout L = count_layout(P, G);
+    o->size = t.size;
+    o->width = t.W;
+    o->stride = t.stride;
+    o->offset = (int64_t)L.arena_off + t.col_off * L.n_pad * (int64_t)sizeof(double);
     return CC_OK;
 }
 

@@ -22,7 +22,7 @@
 // Work split (the neighbour-list partitioning of Section 3.3, Algorithm 4, on wavefronts): every
 // row of at most `hub_threshold` entries is one work item processed by one wavefront; longer rows
 // are cut into chunks of `chunk` entries whose partial neighbour sums go to scratch and are added
-// in chunk order by a second kernel, so every entry has one fixed summation order (no atomics on
+// in a fixed blocked order by a second kernel, so every entry has one fixed summation order (no atomics on
 // counts). Light rows are grouped into ranges of about `chunk` entries (at most 64 rows); chunks and
 // ranges are dealt round-robin to persistent wavefronts.
 #include <hip/hip_runtime.h>
@@ -322,28 +322,40 @@ __device__ __forceinline__ void combine_sets(const StepParams& S, double* orow, 
                                              int lane) {
     if (S.Ws >= kWave / 2) {
         for (int r = lane; r < S.Ws; r += kWave) {
-            double sum = 0.0;
             const uint32_t* sp = S.split + r;
-            int j = 0;
-            // four pairs' loads in flight, then their products added in pair order
-            for (; j + 4 <= S.npairs; j += 4) {
-                uint32_t pr[4];
-                double av[4], nv[4];
+            // pairs in runs of 16 (four pairs' loads in flight, their products added in pair
+            // order), the runs of a group of 16 added in order, then the groups: the blocked
+            // order of blocked_sum, written out to keep the loads in flight
+            double total = 0.0;
+            for (int g = 0; g < S.npairs; g += kSumRun * kSumRun) {
+                const int ge = (S.npairs - g < kSumRun * kSumRun) ? S.npairs : g + kSumRun * kSumRun;
+                double gs = 0.0;
+                for (int b = g; b < ge; b += kSumRun) {
+                    const int be = (ge - b < kSumRun) ? ge : b + kSumRun;
+                    double bs = 0.0;
+                    int j = b;
+                    for (; j + 4 <= be; j += 4) {
+                        uint32_t pr[4];
+                        double av[4], nv[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) pr[q] = sp[(int64_t)(j + q) * S.Ws];
+                        for (int q = 0; q < 4; ++q) pr[q] = sp[(int64_t)(j + q) * S.Ws];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    av[q] = A[pr[q] & 0xFFFFu];
-                    nv[q] = N[pr[q] >> 16];
+                        for (int q = 0; q < 4; ++q) {
+                            av[q] = A[pr[q] & 0xFFFFu];
+                            nv[q] = N[pr[q] >> 16];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) bs += av[q] * nv[q];
+                    }
+                    for (; j < be; ++j) {
+                        const uint32_t pr = sp[(int64_t)j * S.Ws];
+                        bs += A[pr & 0xFFFFu] * N[pr >> 16];
+                    }
+                    gs += bs;
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) sum += av[q] * nv[q];
+                total += gs;
             }
-            for (; j < S.npairs; ++j) {
-                const uint32_t pr = sp[(int64_t)j * S.Ws];
-                sum += A[pr & 0xFFFFu] * N[pr >> 16];
-            }
-            orow[r] = sum;
+            orow[r] = total;
         }
     } else {
         // few outputs: G lanes per output set, pairs strided over 64/G parts, fixed-order reduce
@@ -354,11 +366,13 @@ __device__ __forceinline__ void combine_sets(const StepParams& S, double* orow, 
         const int part = lane / G;
         double sum = 0.0;
         if (r < S.Ws) {
+            // this lane's pairs part, part + parts, ... in blocked order
             const uint32_t* sp = S.split + r;
-            for (int j = part; j < S.npairs; j += parts) {
-                const uint32_t pr = sp[(int64_t)j * S.Ws];
-                sum += A[pr & 0xFFFFu] * N[pr >> 16];
-            }
+            const int mine = (S.npairs - part + parts - 1) / parts;
+            sum = blocked_sum(mine, [&](int i) {
+                const uint32_t pr = sp[(int64_t)(part + i * parts) * S.Ws];
+                return A[pr & 0xFFFFu] * N[pr >> 16];
+            });
         }
         for (int off = G; off < kWave; off <<= 1) sum += __shfl_xor(sum, off);
         if (part == 0 && r < S.Ws) orow[r] = sum;
@@ -429,14 +443,12 @@ __device__ __forceinline__ void do_task(const StepParams& S, int64_t t, double* 
     }
 }
 
-// cut row t of a split: add its chunk partials in chunk order, then combine
+// cut row t of a split: add its chunk partials in the fixed blocked order, then combine
 __device__ __forceinline__ void do_hub(const StepParams& S, int64_t t, double* N, double* Ash, int lane) {
     const HubItem h = S.hubs[t];
     for (int r = lane; r < S.Nw; r += kWave) {
-        double sum = 0.0;
         const double* pp = S.partial + h.first_chunk * S.nstride + r;
-        for (int c = 0; c < h.n_chunks; ++c) sum += pp[(int64_t)c * S.nstride];
-        N[r] = sum;
+        N[r] = blocked_sum(h.n_chunks, [&](int c) { return pp[(int64_t)c * S.nstride]; });
     }
     wave_sync_lds();
     combine_store(S, h.v, N, Ash, lane);

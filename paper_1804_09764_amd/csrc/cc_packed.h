@@ -224,10 +224,10 @@ __device__ inline void pcombine(const StepParams& S, int v, const uint8_t* cvrow
             const double* Nb = N + bl * Cf;
             const uint16_t* eb = eml + cv * Nw;
             const uint32_t* sp = M.sp + r;
-            for (int j = 0; j < S.npairs; ++j) {
+            sum = blocked_sum(S.npairs, [&](int j) {
                 const uint32_t pr = sp[(int64_t)j * Ws];
-                sum += Ab[pr & 0xFFFFu] * Nb[eb[pr >> 16]];
-            }
+                return Ab[pr & 0xFFFFu] * Nb[eb[pr >> 16]];
+            });
         }
         orow[f] = sum;
     }
@@ -284,7 +284,7 @@ __device__ void do_ptask(const StepParams& S, int64_t t, double* N, double* Ash,
     }
 }
 
-// cut row t: chunk partials added in chunk order, then the combine
+// cut row t: chunk partials added in the fixed blocked order, then the combine
 __device__ inline void do_phub(const StepParams& S, int64_t t, double* N, double* Ash, const PMaps& M, int lane) {
     const HubItem h = S.hubs[t];
     const uint8_t* cvall = S.colour + (int64_t)h.v * S.B;
@@ -292,10 +292,8 @@ __device__ inline void do_phub(const StepParams& S, int64_t t, double* N, double
         const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
         pstage_a(S, h.v, b0, nb, Ash, lane);
         for (int i = lane; i < nb * S.Cf; i += kWave) {
-            double sum = 0.0;
             const double* pp = S.partial + h.first_chunk * S.nstride + (int64_t)b0 * S.Cf + i;
-            for (int c = 0; c < h.n_chunks; ++c) sum += pp[(int64_t)c * S.nstride];
-            N[i] = sum;
+            N[i] = blocked_sum(h.n_chunks, [&](int c) { return pp[(int64_t)c * S.nstride]; });
         }
         wave_sync_lds();
         pcombine(S, h.v, cvall + b0, b0, nb, N, Ash, M, lane);

@@ -60,7 +60,9 @@ __global__ __launch_bounds__(256) void k_transpose_colours(const uint8_t* __rest
     }
 }
 
-// per-colouring sums of x[v][b]: block (range, 64 colourings), fixed order within and across blocks
+// per-colouring sums of x[v][b]: block (range, 64 colourings); each thread adds its vertices in the
+// blocked order, the four threads of a colouring are added in order, then the block sums in the
+// blocked order
 __global__ __launch_bounds__(256) void k_reduce_packed_blocks(const double* __restrict__ x, int64_t n, int B,
                                                               int64_t per_block, double* __restrict__ partial) {
     __shared__ double sh[256];
@@ -69,8 +71,10 @@ __global__ __launch_bounds__(256) void k_reduce_packed_blocks(const double* __re
     const int64_t lo = blockIdx.x * per_block;
     const int64_t hi = lo + per_block < n ? lo + per_block : n;
     double s = 0.0;
-    if (b < B)
-        for (int64_t v = lo + tv; v < hi; v += 4) s += x[v * B + b];
+    if (b < B && lo + tv < hi) {
+        const int m = (int)((hi - lo - tv + 3) / 4);  // this thread's vertices lo + tv, lo + tv + 4, ...
+        s = blocked_sum(m, [&](int i) { return x[(lo + tv + 4 * (int64_t)i) * B + b]; });
+    }
     sh[threadIdx.x] = s;
     __syncthreads();
     if (tv == 0 && b < B) partial[(int64_t)blockIdx.x * B + b] = ((sh[tb] + sh[64 + tb]) + sh[128 + tb]) + sh[192 + tb];
@@ -80,9 +84,7 @@ __global__ __launch_bounds__(256) void k_reduce_packed_final(const double* __res
                                                              double* __restrict__ out) {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
-    double s = 0.0;
-    for (int i = 0; i < blocks; ++i) s += partial[(int64_t)i * B + b];
-    out[b] = s;
+    out[b] = blocked_sum(blocks, [&](int i) { return partial[(int64_t)i * B + b]; });
 }
 
 // ---------------------------------------------------------------------------------------------
