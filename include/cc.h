@@ -118,13 +118,19 @@ cc_status cc_plan_split_get(const cc_plan* plan, int32_t i, int32_t* s, int32_t*
  *              or 0xFFFF when its set holds col(v);
  *   mask_off:  p >= 2: u16 [W(p)], the colour set of passive entry j over the k-1 colours other
  *              than the neighbour's;
- *   full_off, emap_off: the packed layout's maps (colour sets over all k colours).
+ *   full_off, emap_off: the packed layout's maps (colour sets over all k colours);
+ *   proj_src_off, proj_fold_off: splits whose passive rows exceed 64 entries (Wn > 0): u16
+ *              [k][k][Wn], Wn = C(k-2, p-1): for a neighbour of colour cu and a centre of colour
+ *              cv, the storage positions of the passive entries whose set avoids cv, in increasing
+ *              order of their colex rank in N, and those ranks (the projected rows, cc_tuning).
  * act, pas: table ids read (-1: a single vertex); out: table id written (-2: the full template).
  * For inspection and host-side checks of the planner; no count call needs it. CC_ERANGE for i out
  * of range, CC_EINVAL for NULL arguments. */
 typedef struct {
     int32_t act, pas, out;
     int64_t split_off, fold_off, mask_off, full_off, emap_off;
+    int64_t proj_src_off, proj_fold_off;
+    int32_t Wn;
 } cc_split_maps;
 
 cc_status cc_plan_split_maps(const cc_plan* plan, int32_t i, cc_split_maps* out);
@@ -164,6 +170,16 @@ typedef struct {
     int32_t hub_threshold;  /* rows with more neighbours than this are cut into chunks (0 = auto) */
     int32_t chunk;          /* neighbours per chunk of a cut row (0 = auto; multiple of 64) */
     int32_t cols_per_lane;  /* passive-row doubles each lane holds per pass: 1, 2, 4, 8 or 16 (0 = auto) */
+    /* projected passive rows for splits whose passive rows exceed 64 entries: a centre of colour c
+     * adds up only the neighbour entries whose colour set avoids c (Eq. 1: the active and passive
+     * colour sets are disjoint), so the count can copy those entries of every row into one
+     * contiguous row per colour and run the split's centres colour class by colour class, a few
+     * classes per pass, reading whole 128-byte lines that hold only needed entries.
+     * 0 = auto (a byte model per split and graph decides; the copies take at most as much
+     * workspace as the table arena), -1 = never, 1..16 = always, this many colour classes per
+     * pass. Results are exact below 2^53 either way, and bit-identical when a passive row fits in
+     * one pass of the gather (the same terms reach each sum in the same order). */
+    int32_t proj_classes;
 } cc_tuning;
 
 /* flags for cc_graph_prepare */
@@ -188,7 +204,7 @@ typedef struct {
     int64_t n, nnz;
     int64_t max_degree;
     int64_t n_light, n_hubs, n_chunks;
-    int32_t hub_threshold, chunk, cols_per_lane;
+    int32_t hub_threshold, chunk, cols_per_lane, proj_classes;
 } cc_graph_info;
 
 cc_status cc_graph_info_get(const cc_graph* g, cc_graph_info* out);
@@ -213,9 +229,16 @@ cc_status cc_color(const cc_graph* g, int32_t k, uint64_t seed, uint64_t first_i
 /* ------------------------------------------------------------------------------------------ */
 
 /* Device workspace needed by cc_count for this plan on this graph (independent of B): the live
- * count tables, the cut rows' chunk partials, the root row, the reduction scratch and the
- * per-CSR-entry neighbour colours of one colouring (nnz bytes). */
+ * count tables, the cut rows' chunk partials, the root row, the reduction scratch, the
+ * per-CSR-entry neighbour colours of one colouring (nnz bytes) and, when a split runs on projected
+ * passive rows (cc_tuning.proj_classes), the projected rows of one pass. */
 cc_status cc_count_workspace_bytes(const cc_plan* plan, const cc_graph* g, size_t* bytes);
+
+/* How cc_count runs each split of this plan on this graph: classes[i] = colour classes per pass
+ * of split i on projected passive rows (cc_tuning.proj_classes), 0 when split i reads the passive
+ * table itself. `classes` is host memory of n >= info.n_splits entries. Host-only. CC_EINVAL for
+ * NULL arguments or a short array. */
+cc_status cc_count_projection(const cc_plan* plan, const cc_graph* g, int32_t* classes, int32_t n);
 
 /*
  * For b in [0, B): X_dev[b] = number of colourful labelled embeddings of T in G under colouring

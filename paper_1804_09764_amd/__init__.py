@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_PKG, "libcc.so")
 CC_PLAN_CENTRE_SMALLEST = 1
 CC_PLAN_NO_SHARING = 2
 CC_GRAPH_TRUST = 1
+CC_MAX_PACKED = 4096  # largest B of one packed count
 
 _STATUS = {0: "CC_OK", -1: "CC_EINVAL", -2: "CC_ERANGE", -3: "CC_ENOMEM", -4: "CC_ENOSPC",
            -5: "CC_EDEVICE", -6: "CC_EINTERNAL"}
@@ -50,7 +51,8 @@ class _PlanInfo(ctypes.Structure):
 class _SplitMaps(ctypes.Structure):
     _fields_ = [("act", ctypes.c_int32), ("pas", ctypes.c_int32), ("out", ctypes.c_int32),
                 ("split_off", ctypes.c_int64), ("fold_off", ctypes.c_int64), ("mask_off", ctypes.c_int64),
-                ("full_off", ctypes.c_int64), ("emap_off", ctypes.c_int64)]
+                ("full_off", ctypes.c_int64), ("emap_off", ctypes.c_int64),
+                ("proj_src_off", ctypes.c_int64), ("proj_fold_off", ctypes.c_int64), ("Wn", ctypes.c_int32)]
 
 
 class _TableDesc(ctypes.Structure):
@@ -62,7 +64,7 @@ class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("n_light", ctypes.c_int64), ("n_hubs", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
                 ("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("cols_per_lane", ctypes.c_int32)]
+                ("cols_per_lane", ctypes.c_int32), ("proj_classes", ctypes.c_int32)]
 
 
 class _Instance(ctypes.Structure):
@@ -79,14 +81,14 @@ def CC_BATCH_SHARE(d: int) -> int:
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("cols_per_lane", ctypes.c_int32)]
+                ("cols_per_lane", ctypes.c_int32), ("proj_classes", ctypes.c_int32)]
 
 
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
            "cc_plan_bind_device", "cc_plan_destroy", "cc_entry_order", "cc_plan_split_maps",
            "cc_plan_constants_get", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
-           "cc_count_inspect", "cc_plan_table_get",
+           "cc_count_inspect", "cc_plan_table_get", "cc_count_projection",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
            "cc_multi_create", "cc_multi_info_get", "cc_multi_step_get", "cc_multi_destroy",
            "cc_count_packed_multi_workspace_bytes",
@@ -124,6 +126,7 @@ def lib() -> ctypes.CDLL:
         "cc_count": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_count_inspect": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P]),
         "cc_plan_table_get": (ctypes.c_int, [P, P, I32, ctypes.POINTER(_TableDesc)]),
+        "cc_count_projection": (ctypes.c_int, [P, P, P, I32]),
         "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_stream_check": (ctypes.c_int, [P]),
@@ -266,14 +269,14 @@ class Graph:
     """A CSR graph resident on the GPU (int64 row_ptr, int32 col) with its prepared work lists."""
 
     def __init__(self, row_ptr, col, hub_threshold: int = 0, chunk: int = 0, trust: bool = False,
-                 cols_per_lane: int = 0, stream=None):
+                 cols_per_lane: int = 0, proj_classes: int = 0, stream=None):
         import torch
         self.row_ptr = row_ptr
         self.col = col
         n = row_ptr.numel() - 1
         nnz = col.numel()
         self.n, self.nnz = n, nnz
-        tun = _Tuning(hub_threshold, chunk, cols_per_lane)
+        tun = _Tuning(hub_threshold, chunk, cols_per_lane, proj_classes)
         nb = ctypes.c_size_t()
         _check(lib().cc_graph_workspace_bytes(n, nnz, ctypes.byref(tun), ctypes.byref(nb)))
         self._ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=row_ptr.device)
@@ -378,6 +381,14 @@ def count_inspect(plan: Plan, graph: Graph, colours, last: int, workspace: Works
                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                   _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
     return ws, V
+
+
+def count_projection(plan: Plan, graph: Graph) -> list[int]:
+    """Colour classes per projected pass of each split in cc_count (0: unprojected)."""
+    n = plan.info.n_splits
+    out = (ctypes.c_int32 * max(n, 1))()
+    _check(lib().cc_count_projection(plan.handle, graph.handle, out, max(n, 1)))
+    return [int(x) for x in out[:n]]
 
 
 def table_desc(plan: Plan, graph: Graph, table: int) -> dict:

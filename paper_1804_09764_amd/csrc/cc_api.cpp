@@ -60,9 +60,46 @@ GraphLayout graph_layout(int64_t n, int64_t nnz, int32_t thr, int32_t chunk) {
     return L;
 }
 
+// Colour classes per projected pass of each split (0: the split reads the passive table itself).
+// Auto: a split is projected when its projected rows hold at least 30 % fewer 128-byte lines than
+// a centre reads from a stored row (measured on R-MAT 23 / edge factor 256: projected rows stream
+// about 10 % slower, so the 462-entry rows of 12-vertex templates, 16 lines instead of 21.7, gain
+// 16 %, while the 330-entry rows, 14 instead of 17.5, lose 3 %) and the lines it saves on the
+// neighbour reads exceed twice the bytes of making the copies (each pass reads the table once;
+// every vertex writes one row per other colour); a pass takes as many classes as fit in the table
+// arena's size.
+std::vector<int> projection_plan(const cc_plan* P, const cc_graph* G, int64_t n_pad) {
+    std::vector<int> g(P->splits.size(), 0);
+    const int k = P->k;
+    const int mode = G->proj_classes;
+    if (mode < 0 || G->n == 0) return g;
+    const double arena_bytes = (double)P->arena_cols * (double)n_pad * sizeof(double);
+    for (size_t i = 0; i < P->splits.size(); ++i) {
+        const cc::Split& sp = P->splits[i];
+        if (sp.Wn <= 0) continue;
+        const double per_class = (double)n_pad * sp.Wn_pad * sizeof(double);
+        int cls;
+        if (mode > 0) {
+            cls = std::min(mode, k);
+        } else {
+            cls = (int)std::max(1.0, std::min((double)k, std::floor(arena_bytes / per_class)));
+            const int passes = (k + cls - 1) / cls;
+            if (sp.lines_need < 1.3 * (sp.Wn_pad / 16.0)) continue;
+            const double saved = (double)G->nnz * (k - 1) / k * 128.0 * (sp.lines_need - sp.Wn_pad / 16.0);
+            const double cost = (double)G->n * sizeof(double) *
+                                ((double)passes * cc::pad_stride(sp.Wp) + (double)(k - 1) * sp.Wn_pad);
+            if (!(saved > 2.0 * cost)) continue;
+        }
+        const int passes = (k + cls - 1) / cls;
+        g[i] = (k + passes - 1) / passes;  // the same number of classes in every pass, give or take one
+    }
+    return g;
+}
+
 struct CountLayout {
-    size_t arena_off, partial_off, root_off, red_off, ecol_off, total;
+    size_t arena_off, partial_off, root_off, red_off, ecol_off, proj_off, total;
     int64_t n_pad;
+    std::vector<int> proj;  // classes per projected pass of each split (0: none)
 };
 
 CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
@@ -73,7 +110,12 @@ CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
     L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)P->max_stride_N * sizeof(double));
     L.red_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * sizeof(double));
     L.ecol_off = align256(L.red_off + 1024 * sizeof(double));
-    L.total = align256(L.ecol_off + (size_t)std::max<int64_t>(G->nnz, 1));
+    L.proj_off = align256(L.ecol_off + (size_t)std::max<int64_t>(G->nnz, 1));
+    L.proj = projection_plan(P, G, L.n_pad);
+    size_t proj_bytes = 0;
+    for (size_t i = 0; i < P->splits.size(); ++i)
+        proj_bytes = std::max(proj_bytes, (size_t)L.proj[i] * (size_t)L.n_pad * (size_t)P->splits[i].Wn_pad * sizeof(double));
+    L.total = align256(L.proj_off + proj_bytes);
     return L;
 }
 
@@ -128,6 +170,8 @@ cc::StepParams base_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     h.split = sp.split_off >= 0 ? (const uint32_t*)(cdev + sp.split_off) : nullptr;
     h.mask = sp.mask_off >= 0 ? (const uint16_t*)(cdev + sp.mask_off) : nullptr;
     h.cols_per_lane = G->cols_per_lane;
+    h.cls_mask = cc::kAllClasses;
+    h.class_stride = 0;
     h.k = P->k;
     h.s = sp.s;
     h.a = sp.a;
@@ -327,6 +371,9 @@ cc_status cc_plan_split_maps(const cc_plan* P, int32_t i, cc_split_maps* o) {
     o->mask_off = sp.mask_off;
     o->full_off = sp.full_off;
     o->emap_off = sp.emap_off;
+    o->proj_src_off = sp.proj_src_off;
+    o->proj_fold_off = sp.proj_fold_off;
+    o->Wn = sp.Wn;
     return CC_OK;
 }
 
@@ -418,6 +465,8 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     if (n >= ((int64_t)1 << 31)) return fail(CC_ERANGE, "n must be below 2^31");
     int32_t thr, chunk, cols;
     resolve_tuning(nnz, tuning, &thr, &chunk, &cols);
+    if (tuning && (tuning->proj_classes < -1 || tuning->proj_classes > CC_MAX_K))
+        return fail(CC_EINVAL, "proj_classes must be -1, 0 or 1..16");
     if (cols != 0 && cols != 1 && cols != 2 && cols != 4 && cols != 8 && cols != 16)
         return fail(CC_EINVAL, "cols_per_lane must be 0, 1, 2, 4, 8 or 16");
     GraphLayout L = graph_layout(n, nnz, thr, chunk);
@@ -518,6 +567,7 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     G->hub_threshold = thr;
     G->chunk = chunk;
     G->cols_per_lane = cols;
+    G->proj_classes = tuning ? tuning->proj_classes : 0;
     e = hipGetDevice(&G->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&G->n_cu, hipDeviceAttributeMultiprocessorCount, G->device);
     if (e == hipSuccess && !light.empty())
@@ -548,6 +598,7 @@ cc_status cc_graph_info_get(const cc_graph* G, cc_graph_info* o) {
     o->hub_threshold = G->hub_threshold;
     o->chunk = G->chunk;
     o->cols_per_lane = G->cols_per_lane;
+    o->proj_classes = G->proj_classes;
     return CC_OK;
 }
 
@@ -569,6 +620,14 @@ cc_status cc_count_workspace_bytes(const cc_plan* P, const cc_graph* G, size_t* 
     return CC_OK;
 }
 
+cc_status cc_count_projection(const cc_plan* P, const cc_graph* G, int32_t* classes, int32_t n) {
+    if (!P || !G || !classes) return fail(CC_EINVAL, "NULL argument");
+    if (n < (int32_t)P->splits.size()) return fail(CC_EINVAL, "classes holds fewer entries than the plan has splits");
+    const std::vector<int> g = projection_plan(P, G, pad32(G->n));
+    for (size_t i = 0; i < g.size(); ++i) classes[i] = g[i];
+    return CC_OK;
+}
+
 namespace {
 
 // Splits [0, last] of plan P for one colouring on `st`: the per-entry neighbour colours, then
@@ -581,6 +640,34 @@ hipError_t run_splits(const cc_plan* P, const cc_graph* G, const uint8_t* colour
     // every split reads the colour of each CSR entry's vertex: gathered once per colouring into a
     // sequential array instead of once per split at random
     hipError_t e = cc::launch_edge_colours(G->col, colour, G->nnz, ecol, st);
+    const cc_plan* plan = P;
+    // a projected split: per pass, copy the needed entries of every passive row for the pass's
+    // centre colours, then run the pass's centres on the copies; the cut rows finish at the end
+    auto projected = [&](const cc::Split& sp, const cc::StepParams& h, int cls, hipEvent_t mid) -> hipError_t {
+        const uint8_t* cdev = (const uint8_t*)plan->dev;
+        const int k = plan->k;
+        cc::StepParams hp = h;
+        hp.P = (const double*)(ws + L.proj_off);
+        hp.pstride = sp.Wn_pad;
+        hp.Wp = sp.Wn;
+        hp.fold = (const uint16_t*)(cdev + sp.proj_fold_off);
+        hp.mask = (const uint16_t*)(cdev + sp.proj_mask_off);
+        hp.class_stride = L.n_pad * sp.Wn_pad;
+        hipError_t err = hipSuccess;
+        for (int c0 = 0; err == hipSuccess && c0 < k; c0 += cls) {
+            const int c1 = std::min(k, c0 + cls);
+            uint32_t m = ((1u << c1) - 1u) & ~((1u << c0) - 1u);
+            if (c0 == 0) m |= cc::kAnyInvalid;
+            err = cc::launch_project(h.P, h.pstride, sp.Wp, colour, G->n, k, (const uint16_t*)(cdev + sp.proj_src_off),
+                                     sp.Wn, sp.Wn_pad, hp.class_stride, m & ((1u << k) - 1u),
+                                     (double*)(ws + L.proj_off), st);
+            hp.cls_mask = m;
+            if (err == hipSuccess) err = cc::launch_split_tasks(hp, G->n_cu, st);
+        }
+        if (err == hipSuccess && mid) err = hipEventRecord(mid, st);
+        if (err == hipSuccess) err = cc::launch_hub_finish(h, G->n_cu, st);
+        return err;
+    };
     for (int64_t i = 0; e == hipSuccess && i <= last; ++i) {
         const cc::Split& sp = P->splits[(size_t)i];
         cc::StepParams h = step_params(P, G, sp, colour, arena, L.n_pad, partial, root_out);
@@ -590,7 +677,9 @@ hipError_t run_splits(const cc_plan* P, const cc_graph* G, const uint8_t* colour
             for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
             if (e == hipSuccess) e = hipEventRecord(ev[0], st);
         }
-        if (e == hipSuccess) e = cc::launch_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
+        const int cls = L.proj[(size_t)i];
+        if (e == hipSuccess && cls > 0) e = projected(sp, h, cls, P->profiling ? ev[1] : nullptr);
+        else if (e == hipSuccess) e = cc::launch_split(h, G->n_cu, st, P->profiling ? ev[1] : nullptr);
         if (e == hipSuccess && P->profiling) {
             e = hipEventRecord(ev[2], st);
             auto& pe = P->prof_events[(size_t)i];

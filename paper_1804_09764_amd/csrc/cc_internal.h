@@ -40,6 +40,15 @@ struct Split {
     int Cf;             // C(k, p)
     int64_t full_off;   // byte offset of FM[cu][j]: full-space rank of passive entry j (-1 if p == 1)
     int64_t emap_off;   // byte offset of E[cv][q]: full-space rank of N entry q written without cv
+    // projected passive rows (wide passive rows, p >= 2 and Wp > 64): for a centre colour cv the
+    // entries of a neighbour's row whose set avoids cv, C(k-2, p-1) = Wn of them, in colex order
+    // of the set, copied into a contiguous row of Wn_pad doubles
+    int Wn;               // C(k-2, p-1), 0 if the split has no projected form
+    int Wn_pad;           // Wn rounded up to 16 doubles (whole 128-byte lines)
+    double lines_need;    // expected 128-byte lines of a stored passive row that hold a needed entry
+    int64_t proj_src_off;   // byte offset of S[cu][cv][j]: storage position in u's row of projected entry j
+    int64_t proj_fold_off;  // byte offset of F[cu][cv][j]: N entry of projected entry j
+    int64_t proj_mask_off;  // byte offset of Wn zero masks (every projected entry is needed)
 };
 
 struct Table {
@@ -155,7 +164,16 @@ struct StepParams {
     int cs_off;         // offset of the colour stage of a CSR block (64 * bt bytes)
     const uint16_t* fullmap;  // FM[cu][j] (p >= 2)
     const uint16_t* emap;     // E[cv][q]
+    // centre colours this launch processes: bit c for colour c < k, bit kAnyInvalid for the rows
+    // whose colour is not below k (they only write zeros); all bits set outside projected passes
+    uint32_t cls_mask;
+    // projected passes: the passive row of a neighbour for a centre of colour cv starts at
+    // P + slot(cv) * class_stride, slot(cv) = number of colours below cv in cls_mask; 0 otherwise
+    int64_t class_stride;
 };
+
+constexpr uint32_t kAnyInvalid = 1u << 16;
+constexpr uint32_t kAllClasses = 0x1FFFFu;
 
 // LDS layout of one split: N row (padded), then the active row when a >= 2 and both rows fit in
 // 16 KB per wavefront; wider active rows are read from HBM by the combine, which keeps the
@@ -209,6 +227,17 @@ hipError_t launch_validate(const int64_t* row_ptr, const int32_t* col, int64_t n
                            unsigned* flags, hipStream_t st);
 // mid (optional) is recorded between the gather kernel and the cut-row finish kernel
 hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid);
+// the two halves of launch_split: the task kernel (chunks of cut rows and light rows whose centre
+// colour is in S.cls_mask) and the cut-row finish (every cut row)
+hipError_t launch_split_tasks(StepParams S, int n_cu, hipStream_t st);
+hipError_t launch_hub_finish(StepParams S, int n_cu, hipStream_t st);
+// projected passive rows for the centre colours in cls_mask (bit c: colour c; at most one
+// projected row per (vertex, colour)): out + slot(c) * class_stride + u * qstride holds the Wn
+// entries src[(col(u) * k + c) * Wn + j] of P's row u (W entries), for every u whose colour is
+// below k and other than c
+hipError_t launch_project(const double* P, int64_t pstride, int W, const uint8_t* colour, int64_t n, int k,
+                          const uint16_t* src, int Wn, int64_t qstride, int64_t class_stride, uint32_t cls_mask,
+                          double* out, hipStream_t st);
 // kernel variant of a split (general path with 1/2/4/8 doubles per lane = 0..3, or narrow rows
 // with 16/32 lanes per row = 4/5) and the LDS stage per wavefront a narrow variant adds
 int split_variant(int p, int Wp, int cols_per_lane);
@@ -243,6 +272,7 @@ struct cc_graph {
     int64_t n_light = 0, n_ranges = 0, n_chunks = 0, n_hubs = 0;
     int32_t hub_threshold = 0, chunk = 0;
     int32_t cols_per_lane = 0;
+    int32_t proj_classes = 0;  // cc_tuning.proj_classes
     int device = 0;
     int n_cu = 0;
 };

@@ -64,9 +64,22 @@ struct Idx16 {
     }
 };
 
+// Slot of centre colour cv among the colours of a projected pass (0 outside projected passes,
+// where class_stride is 0).
+__device__ __forceinline__ int class_slot(const StepParams& S, int cv) {
+    return __popc(S.cls_mask & ((1u << cv) - 1u));
+}
+
+// Whether this launch processes a row whose centre has colour cv (rows of colours >= k only write
+// zeros and belong to the launch that holds kAnyInvalid).
+__device__ __forceinline__ bool class_in(const StepParams& S, int cv) {
+    return cv < S.k ? ((S.cls_mask >> cv) & 1u) != 0 : (S.cls_mask & kAnyInvalid) != 0;
+}
+
 template <int J, int D>
-__device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, int su, int sc, int c0, int cv,
-                                           int lane, const Idx16<J>& msk, double (&X)[D][J], Idx16<J> (&F)[D]) {
+__device__ __forceinline__ void load_batch(const StepParams& S, const double* Pb, int b, int cnt, int su, int sc,
+                                           int c0, int cv, int lane, const Idx16<J>& msk, double (&X)[D][J],
+                                           Idx16<J> (&F)[D]) {
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         const int i = b * D + q;
@@ -76,7 +89,7 @@ __device__ __forceinline__ void load_batch(const StepParams& S, int b, int cnt, 
             // position of col(v) among the colours other than col(u): entries whose set holds it
             // are dropped by the fold, so they are not loaded (whole cache lines are skipped)
             const int x = cv - (cv > ci ? 1 : 0);
-            const double* row = S.P + (int64_t)ui * S.pstride + c0;
+            const double* row = Pb + (int64_t)ui * S.pstride + c0;
 #pragma unroll
             for (int t = 0; t < J; ++t) {
                 const bool need = ((msk.get(t) >> x) & 1) == 0;
@@ -137,6 +150,8 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
     constexpr int D = (J >= 6) ? 1 : (J >= 4) ? 2 : 4;  // rows per batch: two batches within the VGPR budget
     const int k = S.k;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // the passive rows: the table itself, or in a projected pass the copy for this centre colour
+    const double* Pb = S.P + (int64_t)class_slot(S, cv) * S.class_stride;
     for (int c0 = 0; c0 < S.Wp; c0 += kWave * J) {
         // colour-set masks of this lane's columns; columns past the row get an all-ones mask,
         // which marks them as never needed
@@ -178,12 +193,12 @@ __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int c
             }
             int cur = -1;
             const int nb = (cnt + D - 1) / D;
-            load_batch<J, D>(S, 0, cnt, su, sc, c0, cv, lane, msk, XA, FA);
+            load_batch<J, D>(S, Pb, 0, cnt, su, sc, c0, cv, lane, msk, XA, FA);
             for (int b = 0; b < nb; b += 2) {
-                if (b + 1 < nb) load_batch<J, D>(S, b + 1, cnt, su, sc, c0, cv, lane, msk, XB, FB);
+                if (b + 1 < nb) load_batch<J, D>(S, Pb, b + 1, cnt, su, sc, c0, cv, lane, msk, XB, FB);
                 consume_batch<J, D>(b, cnt, sc, cur, N, acc, fcur, XA, FA);
                 if (b + 1 >= nb) break;
-                if (b + 2 < nb) load_batch<J, D>(S, b + 2, cnt, su, sc, c0, cv, lane, msk, XA, FA);
+                if (b + 2 < nb) load_batch<J, D>(S, Pb, b + 2, cnt, su, sc, c0, cv, lane, msk, XA, FA);
                 consume_batch<J, D>(b + 1, cnt, sc, cur, N, acc, fcur, XB, FB);
             }
             fold_acc<J>(N, acc, fcur);
@@ -215,6 +230,7 @@ __device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end
         fidx[m] = (colok && c < k && c != cv) ? (int)S.fold[((int64_t)c * k + cv) * S.Wp + j] : (int)kNoSlot;
     }
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const double* Pb = S.P + (int64_t)class_slot(S, cv) * S.class_stride;
     for (int64_t e0 = beg; e0 < end; e0 += kWave) {
         const int64_t e = e0 + lane;
         const bool valid = e < end;
@@ -240,7 +256,7 @@ __device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end
             const int cq = __shfl(sc, i);
             const int xpos = cv - (cv > cq ? 1 : 0);
             const bool need = i < cnt && ((mskj >> xpos) & 1) == 0;
-            x[q] = need ? S.P[(int64_t)uq * S.pstride + j] : 0.0;
+            x[q] = need ? Pb[(int64_t)uq * S.pstride + j] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) stage[(q * R + g) * G + j] = x[q];
@@ -405,6 +421,7 @@ __device__ __forceinline__ void light_row(const StepParams& S, int v, double* N,
     const int64_t end = S.row_ptr[v + 1];
     // a vertex without a valid colour (>= k) roots no colourful embedding
     const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[(int64_t)v * S.cstride]);
+    if (!class_in(S, cv)) return;  // another pass of a projected split owns this row
     if (beg == end || cv >= S.k) {
         double* orow = S.O + (int64_t)v * S.ostride;
         for (int r = lane; r < S.Ws; r += kWave) orow[r] = 0.0;
@@ -426,6 +443,7 @@ __device__ __forceinline__ void do_task(const StepParams& S, int64_t t, double* 
         const ChunkItem ch = S.chunks[t];
         const int v = __builtin_amdgcn_readfirstlane(ch.v);
         const int cv = __builtin_amdgcn_readfirstlane((int)S.colour[(int64_t)v * S.cstride]);
+        if (!class_in(S, cv)) return;  // another pass of a projected split owns this chunk
         for (int r = lane; r < S.Nw; r += kWave) N[r] = 0.0;
         wave_sync_lds();
         if (cv < S.k) {
@@ -481,6 +499,60 @@ __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
     for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves)
         do_hub(S, t, N, Ash, lane);
+}
+
+// Projected passive rows for one pass of a split: for each vertex u that has a colour cu below k,
+// and each centre colour c of the pass other than cu, the entries of u's row whose colour set
+// avoids c (the only ones a centre of colour c adds up), in colex order of the set, as one
+// contiguous row. One wavefront per vertex: the row is read once from HBM (staged in LDS when it
+// holds at most kProjStage entries), then each copy gathers its entries with all index loads and
+// value loads of a lane issued before its stores.
+constexpr int kProjStage = 1024;
+
+template <bool STAGE>
+__global__ __launch_bounds__(256) void k_project(const double* __restrict__ P, int64_t pstride, int W,
+                                                 const uint8_t* __restrict__ colour, int64_t n, int k,
+                                                 const uint16_t* __restrict__ src, int Wn, int64_t qstride,
+                                                 int64_t class_stride, uint32_t cls_mask, double* __restrict__ out) {
+    __shared__ double stage[STAGE ? 4 * kProjStage : 1];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    double* row_sh = stage + (STAGE ? wib * kProjStage : 0);
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t n_waves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t u = wave; u < n; u += n_waves) {
+        const int cu = __builtin_amdgcn_readfirstlane((int)colour[u]);
+        if (cu >= k) continue;
+        const double* prow = P + u * pstride;
+        if constexpr (STAGE) {
+            for (int j = lane; j < W; j += kWave) row_sh[j] = prow[j];
+            wave_sync_lds();
+        }
+        for (int c = 0; c < k; ++c) {
+            if (c == cu || !((cls_mask >> c) & 1u)) continue;
+            const int slot = __popc(cls_mask & ((1u << c) - 1u));
+            const uint16_t* sm = src + ((int64_t)cu * k + c) * Wn;
+            double* orow = out + (int64_t)slot * class_stride + u * qstride;
+            for (int j0 = 0; j0 < Wn; j0 += 4 * kWave) {
+                int idx[4];
+                double val[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = j0 + q * kWave + lane;
+                    idx[q] = j < Wn ? (int)sm[j] : -1;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (STAGE) val[q] = idx[q] >= 0 ? row_sh[idx[q]] : 0.0;
+                    else val[q] = idx[q] >= 0 ? prow[idx[q]] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (idx[q] >= 0) orow[j0 + q * kWave + lane] = val[q];
+            }
+        }
+        if constexpr (STAGE) wave_sync_lds();  // the next row overwrites the stage
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -785,7 +857,28 @@ static int waves_for_lds(int lds_wave) {
     return best;
 }
 
-hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) {
+hipError_t launch_project(const double* P, int64_t pstride, int W, const uint8_t* colour, int64_t n, int k,
+                          const uint16_t* src, int Wn, int64_t qstride, int64_t class_stride, uint32_t cls_mask,
+                          double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (W <= kProjStage)
+        hipLaunchKernelGGL(k_project<true>, dim3(grid_for(n, 4, 65536)), dim3(256), 0, st, P, pstride, W, colour, n, k,
+                           src, Wn, qstride, class_stride, cls_mask, out);
+    else
+        hipLaunchKernelGGL(k_project<false>, dim3(grid_for(n, 4, 65536)), dim3(256), 0, st, P, pstride, W, colour, n, k,
+                           src, Wn, qstride, class_stride, cls_mask, out);
+    return hipGetLastError();
+}
+
+// launch geometry of a split (both kernels use the same workgroup shape and LDS slice)
+struct SplitLaunch {
+    const void* fn;
+    int threads;
+    size_t lds;
+};
+
+static hipError_t split_geometry(StepParams* Sp, SplitLaunch* L) {
+    StepParams& S = *Sp;
     // narrow passive rows take G lanes per row (a stage of 64 rows in LDS) unless a width is forced
     const int narrow = (S.p >= 2 && S.cols_per_lane == 0 && S.Wp <= 32) ? (S.Wp <= 16 ? 16 : 32) : 0;
     S.a_off = split_a_off(S.Nw);
@@ -810,37 +903,54 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
         case 8: fn = (const void*)k_split<8, 0>; break;
         default: fn = (const void*)k_split<16, 0>; break;
     }
+    L->fn = fn;
+    L->threads = threads;
+    L->lds = lds;
+    return hipSuccess;
+}
+
+hipError_t launch_split_tasks(StepParams S, int n_cu, hipStream_t st) {
+    SplitLaunch L;
+    hipError_t err = split_geometry(&S, &L);
+    if (err != hipSuccess) return err;
     int per_cu = 0;
-    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, L.fn, L.threads, L.lds);
     if (err != hipSuccess) return err;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     const int64_t total = S.n_chunks + S.n_ranges;
     int64_t blocks = (int64_t)per_cu * n_cu;
-    const int64_t need = (total + waves_per_block - 1) / waves_per_block;
+    const int64_t need = (total + S.waves_per_block - 1) / S.waves_per_block;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
     if (total > 0) {
         void* args[] = {&S};
-        err = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(threads), args, lds, st);
+        err = hipLaunchKernel(L.fn, dim3((unsigned)blocks), dim3(L.threads), args, L.lds, st);
         if (err != hipSuccess) return err;
         err = hipGetLastError();
-        if (err != hipSuccess) return err;
     }
-    if (mid) {
-        err = hipEventRecord(mid, st);
-        if (err != hipSuccess) return err;
-    }
-    if (S.n_hubs > 0) {
-        int per_cu2 = 0;
-        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_hub_finish, threads, lds);
-        if (err != hipSuccess) return err;
-        if (per_cu2 < 1) return hipErrorInvalidConfiguration;
-        int64_t b2 = (int64_t)per_cu2 * n_cu;
-        const int64_t need2 = (S.n_hubs + waves_per_block - 1) / waves_per_block;
-        if (b2 > need2) b2 = need2;
-        hipLaunchKernelGGL(k_hub_finish, dim3((unsigned)b2), dim3(threads), lds, st, S);
-        err = hipGetLastError();
-    }
+    return err;
+}
+
+hipError_t launch_hub_finish(StepParams S, int n_cu, hipStream_t st) {
+    if (S.n_hubs <= 0) return hipSuccess;
+    SplitLaunch L;
+    hipError_t err = split_geometry(&S, &L);
+    if (err != hipSuccess) return err;
+    int per_cu2 = 0;
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_hub_finish, L.threads, L.lds);
+    if (err != hipSuccess) return err;
+    if (per_cu2 < 1) return hipErrorInvalidConfiguration;
+    int64_t b2 = (int64_t)per_cu2 * n_cu;
+    const int64_t need2 = (S.n_hubs + S.waves_per_block - 1) / S.waves_per_block;
+    if (b2 > need2) b2 = need2;
+    hipLaunchKernelGGL(k_hub_finish, dim3((unsigned)b2), dim3(L.threads), L.lds, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) {
+    hipError_t err = launch_split_tasks(S, n_cu, st);
+    if (err == hipSuccess && mid) err = hipEventRecord(mid, st);
+    if (err == hipSuccess) err = launch_hub_finish(S, n_cu, st);
     return err;
 }
 

@@ -588,6 +588,12 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
         sp.mask_off = -1;
         sp.full_off = -1;
         sp.emap_off = -1;
+        sp.Wn = 0;
+        sp.Wn_pad = 0;
+        sp.lines_need = 0.0;
+        sp.proj_src_off = -1;
+        sp.proj_fold_off = -1;
+        sp.proj_mask_off = -1;
         sp.Cf = (int)binom(k, sp.p);
         // storage orders of the output, active and passive rows (tables of equal size share one)
         const std::vector<int>& order_s = order_of(sp.s - 1);
@@ -644,6 +650,56 @@ cc_status plan_build(int k, const int32_t* edges, int root, uint32_t flags, cc_p
                 }
             const uint8_t* b = reinterpret_cast<const uint8_t*>(tab.data());
             C.insert(C.end(), b, b + tab.size() * 2);
+            // expected 128-byte lines of a stored row holding an entry a centre needs (the
+            // centre's colour is uniform over the k-1 colours of the row)
+            {
+                const size_t W = rows.size();
+                int64_t lines = 0;
+                for (int x = 0; x < K; ++x)
+                    for (size_t l = 0; l < W; l += 16) {
+                        bool any = false;
+                        for (size_t j = l; j < std::min(W, l + 16); ++j) any = any || !((rows[j] >> x) & 1u);
+                        lines += any ? 1 : 0;
+                    }
+                sp.lines_need = K > 0 ? (double)lines / K : 0.0;
+            }
+            if (sp.Wp > 64) {
+                // projected rows: for (cu, cv) the storage positions j whose fold target is a slot,
+                // ordered by that slot (the colex rank of the set over the colours other than cv),
+                // and the slots themselves; Wn = C(k-2, p-1) of them for cu != cv
+                sp.Wn = (int)binom(k - 2, sp.p - 1);
+                sp.Wn_pad = pad_stride(sp.Wn);
+                const size_t W = rows.size(), Wn = (size_t)sp.Wn;
+                std::vector<uint16_t> src((size_t)k * k * Wn, 0), dst((size_t)k * k * Wn, kNoSlot);
+                for (int cu = 0; cu < k; ++cu)
+                    for (int cv = 0; cv < k; ++cv) {
+                        if (cu == cv) continue;
+                        const uint16_t* f = &tab[((size_t)cu * k + cv) * W];
+                        std::vector<std::pair<uint16_t, uint16_t>> need;
+                        for (size_t j = 0; j < W; ++j)
+                            if (f[j] != kNoSlot) need.push_back({f[j], (uint16_t)j});
+                        std::sort(need.begin(), need.end());
+                        if (need.size() != Wn) {
+                            *err = "internal: projected row width";
+                            return CC_EINTERNAL;
+                        }
+                        for (size_t q = 0; q < Wn; ++q) {
+                            src[((size_t)cu * k + cv) * Wn + q] = need[q].second;
+                            dst[((size_t)cu * k + cv) * Wn + q] = need[q].first;
+                        }
+                    }
+                align();
+                sp.proj_src_off = (int64_t)C.size();
+                const uint8_t* bs = reinterpret_cast<const uint8_t*>(src.data());
+                C.insert(C.end(), bs, bs + src.size() * 2);
+                align();
+                sp.proj_fold_off = (int64_t)C.size();
+                const uint8_t* bd = reinterpret_cast<const uint8_t*>(dst.data());
+                C.insert(C.end(), bd, bd + dst.size() * 2);
+                align();
+                sp.proj_mask_off = (int64_t)C.size();
+                C.insert(C.end(), Wn * 2, 0);
+            }
             // set of passive entry j as a bit mask over the k-1 colours other than the
             // neighbour's: entry j is of no use to v when it contains col(v)'s position there
             align();

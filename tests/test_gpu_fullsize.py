@@ -108,11 +108,18 @@ def test_rmat23_ef256_closed_forms_and_invariance(dev):
     T = inputs.pruefer_tree(12, 12)
     c12 = cc.colour(G, 12, seed=777, first_iter=0, B=1)
     print("case: R-MAT 23 ef256, 12-tree, two roots", flush=True)
-    Xa = cc.count(cc.Plan(T), G, c12)
+    Pa = cc.Plan(T)
+    # the byte model projects the 462-entry passive rows of the (7, 1, 6) split only
+    proj = cc.count_projection(Pa, G)
+    assert [i for i, c in enumerate(proj) if c > 0] == [i for i, sp in enumerate(Pa.splits) if sp[2] == 6]
+    Xa = cc.count(Pa, G, c12)
     Xb = cc.count(cc.Plan(T, root=0), G, c12)
+    # projected and unprojected counts agree bit for bit (each row fits one pass of the gather)
+    Xc = cc.count(Pa, cc.Graph(rp_d, col_d, trust=True, proj_classes=-1), c12)
     torch.cuda.synchronize()
     a, b = float(Xa.cpu()[0]), float(Xb.cpu()[0])
     assert a > TWO53 and abs(a - b) <= 1e-12 * a
+    assert float(Xc.cpu()[0]) == a
 
 
 def test_c2_batched_against_oracle(dev):

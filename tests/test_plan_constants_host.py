@@ -179,3 +179,113 @@ def test_masks_and_packed_maps_agree_with_fold_maps(k):
                 f = fold[cu, cv][~dropped]
                 q = pos_of[f] if a == 1 else f
                 np.testing.assert_array_equal(FM[cu][~dropped], E[cv][q])
+
+
+def _colex_masks(K, m):
+    return [x for x in range(1 << K) if bin(x).count("1") == m]
+
+
+def _squeeze(mask, c):
+    """The set `mask` written over the colours other than c (bit c removed, higher bits shifted)."""
+    return (mask & ((1 << c) - 1)) | ((mask >> (c + 1)) << c)
+
+
+@pytest.mark.parametrize("k", [10, 12, 14])
+def test_projected_maps_name_the_needed_sets(k):
+    """Projected rows: for a neighbour of colour cu and a centre of colour cv, entry j is the j-th
+    colour set Q (|Q| = p, cu in Q, cv not in Q) in colex order; its source is the position of
+    Q \\ {cu} in the neighbour's stored row and its target the rank of Q among the p-sets over the
+    colours other than cv. Derived here from the sets, not from the fold map."""
+    K = k - 1
+    P = cc.Plan(inputs.pruefer_tree(k, 3), bind=False)
+    C = P.constants()
+    seen = 0
+    for i, (s, a, p) in enumerate(P.splits):
+        m = P.split_maps(i)
+        Wp = comb(K, p - 1)
+        if p < 2 or Wp <= 64:
+            assert m["Wn"] == 0 and m["proj_src_off"] == -1
+            continue
+        seen += 1
+        Wn = comb(k - 2, p - 1)
+        assert m["Wn"] == Wn
+        src = _u16(C, m["proj_src_off"], k * k * Wn).reshape(k, k, Wn)
+        dst = _u16(C, m["proj_fold_off"], k * k * Wn).reshape(k, k, Wn)
+        order = cc.entry_order(k, p - 1)
+        pos_of_rank = np.empty(len(order), dtype=np.int64)
+        pos_of_rank[order] = np.arange(len(order))
+        row_rank = {x: r for r, x in enumerate(_colex_masks(K, p - 1))}
+        n_rank = {x: r for r, x in enumerate(_colex_masks(K, p))}
+        for cu in range(k):
+            for cv in range(k):
+                if cu == cv:
+                    continue
+                Qs = [Q for Q in _colex_masks(k, p) if (Q >> cu) & 1 and not (Q >> cv) & 1]
+                assert len(Qs) == Wn
+                want_src = [pos_of_rank[row_rank[_squeeze(Q & ~(1 << cu), cu)]] for Q in Qs]
+                want_dst = [n_rank[_squeeze(Q, cv)] for Q in Qs]
+                np.testing.assert_array_equal(src[cu, cv], want_src)
+                np.testing.assert_array_equal(dst[cu, cv], want_dst)
+    assert seen > 0
+
+
+def host_count_projected(P, rp, cl, col):
+    """Eq. 1 with every wide neighbour sum read through the projected rows: a centre of colour cv
+    adds, for each neighbour u, the row proj[cv][u] = T[u][src[col(u), cv]] at N[dst[col(u), cv]]."""
+    k = P.k
+    K = k - 1
+    C = P.constants()
+    n = len(rp) - 1
+    tables = {}
+    for i, (s, a, p) in enumerate(P.splits):
+        m = P.split_maps(i)
+        Wp, Ws, Nw = comb(K, p - 1), comb(K, s - 1), comb(K, p)
+        N = np.zeros((n, Nw))
+        Tp = tables[m["pas"]] if p >= 2 else None
+        if m["Wn"] > 0:
+            Wn = m["Wn"]
+            src = _u16(C, m["proj_src_off"], k * k * Wn).reshape(k, k, Wn)
+            dst = _u16(C, m["proj_fold_off"], k * k * Wn).reshape(k, k, Wn)
+        elif p >= 2:
+            fold = _u16(C, m["fold_off"], k * k * Wp).reshape(k, k, Wp)
+        for v in range(n):
+            cv = int(col[v])
+            for u in cl[rp[v]:rp[v + 1]]:
+                cu = int(col[u])
+                if cu == cv:
+                    continue
+                if p == 1:
+                    N[v, cu - (cu > cv)] += 1.0
+                elif m["Wn"] > 0:
+                    N[v, dst[cu, cv]] += Tp[u][src[cu, cv]]
+                else:
+                    f = fold[cu, cv]
+                    keep = f != NO
+                    np.add.at(N[v], f[keep], Tp[u][keep])
+        if a == 1:
+            O = N[:, _u32(C, m["split_off"], Ws)]
+        else:
+            npairs = comb(s - 1, p)
+            pairs = _u32(C, m["split_off"], npairs * Ws).reshape(npairs, Ws)
+            O = (tables[m["act"]][:, pairs & 0xFFFF] * N[:, pairs >> 16]).sum(axis=1)
+        if m["out"] == -2:
+            return float(O[:, 0].sum()), O[:, 0]
+        tables[m["out"]] = O
+    raise AssertionError("no split writes the full template")
+
+
+def test_projected_rows_reproduce_oracle():
+    rp, cl = inputs.er_graph(24, 80, 9)
+    n = len(rp) - 1
+    cases = [(k, T) for k in (9, 10, 11, 12) for T in (inputs.path_tree(k), inputs.star_tree(k),
+                                                        inputs.pruefer_tree(k, 4))]
+    wide = 0
+    for ci, (k, T) in enumerate(cases):
+        col = oracle.colour(300 + ci, 0, n, k)
+        P = cc.Plan(T, bind=False)
+        wide += sum(P.split_maps(i)["Wn"] > 0 for i in range(P.info.n_splits))
+        X, V = host_count_projected(P, rp, cl, col)
+        Xo, Vo = oracle.count(rp, cl, col, T, root=P.info.root, per_vertex=True)
+        np.testing.assert_array_equal(V, Vo, err_msg=f"k={k} case {ci}")
+        assert X == Xo
+    assert wide >= 6
