@@ -263,8 +263,9 @@ def bench(args):
     colours = torch.empty((B, n), dtype=torch.uint8, device=dev)
     X = torch.empty(B, dtype=torch.float64, device=dev)
     ws_bytes = cc.count_workspace_bytes(P, G)
+    proj = cc.count_projection(P, G)
     print(f"[bench] plan root={P.info.root} splits={P.splits} workspace={ws_bytes / 1e9:.2f} GB "
-          f"graph={G.info}", file=sys.stderr, flush=True)
+          f"graph={G.info} projected classes per pass={proj}", file=sys.stderr, flush=True)
 
     packed = args.path in ("packed", "auto")
     pack = B
@@ -384,7 +385,7 @@ def bench(args):
     return out
 
 
-def batched_vs_plain(args, reps: int = 2):
+def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
     """Plain vs batched on the batched configuration: R-MAT scale 18 (edge factor 16, seed 2), all
     11 trees with 7 vertices x 64 colourings.
 
@@ -444,10 +445,11 @@ def batched_vs_plain(args, reps: int = 2):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(reps):
+        r = inst_reps if name.startswith("instances") else reps
+        for _ in range(r):
             fn()
         torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0) / reps
+        res[name] = (time.perf_counter() - t0) / r
         print(f"[bench] {name}: {res[name] * 1e3:.1f} ms", file=sys.stderr, flush=True)
         if name == "instances_persistent":
             persistent.check()
@@ -486,35 +488,48 @@ def batched_vs_plain(args, reps: int = 2):
 
 
 SERVE_POOL = [(16 + (i % 7), (8, 16, 32)[i % 3], 100 + i) for i in range(16)]  # (scale, edge factor, seed)
+# request mixes: "full" draws every graph of the pool and 8..128 colourings per request; "light"
+# keeps k in 5..12 but draws only the graphs of scale <= 20 and 8..16 colourings, so that 100 or
+# more requests per arrival rate fit in the benchmark's time
+SERVE_MIXES = {"full": dict(max_scale=22, b_range=(8, 128)), "light": dict(max_scale=20, b_range=(8, 16))}
 
 
-def make_requests(n, pool_size, seed, rate, k_range=(5, 12), b_range=(8, 128), t0=0.0):
+def make_requests(n, pool, seed, rate, k_range=(5, 12), b_range=(8, 128), max_scale=22, t0=0.0):
     """n requests with Poisson arrivals at `rate` per second (all at t0 if rate is 0): a graph
-    uniform over the pool, a Pruefer tree with k uniform in k_range (seeded by the request id),
-    B uniform in b_range colourings."""
+    uniform over the pool's graphs of scale <= max_scale, a Pruefer tree with k uniform in k_range
+    (seeded by the request id), B uniform in b_range colourings. The same seed gives the same
+    requests whatever the rate."""
     import numpy as np
 
     import inputs
     from paper_1804_09764_amd.serving import Request
     rng = np.random.default_rng(seed)
+    arr = np.random.default_rng(seed + 1)
+    gids = [i for i, (scale, _, _) in enumerate(pool) if scale <= max_scale]
     t = t0
     out = []
     for i in range(n):
         if rate > 0:
-            t += rng.exponential(1.0 / rate)
+            t += arr.exponential(1.0 / rate)
         k = int(rng.integers(k_range[0], k_range[1] + 1))
         B = int(rng.integers(b_range[0], b_range[1] + 1))
-        gid = int(rng.integers(0, pool_size))
+        gid = gids[int(rng.integers(0, len(gids)))]
         rid = seed * 100000 + i
         out.append(Request(rid=rid, graph_id=gid, tree_edges=inputs.pruefer_tree(k, rid), B=B, seed=rid, arrival=t))
     return out
 
 
 def serving_leg(args):
-    """Continuous-batching server over 16 resident R-MAT graphs (scale 16..22, edge factor 8..32):
-    first the capacity with all requests queued at once, then Poisson arrivals at 50 %, 80 % and
-    95 % of it; reports served CSEU/s and p50/p99 latency (arrival to result) per load, and the
-    80 % figures as the headline latencies."""
+    """Continuous-batching server over 16 resident R-MAT graphs (scale 16..22, edge factor 8..32).
+
+    One request mix (seed 9) throughout: first the capacity, with all of its requests queued at
+    once; then the same requests with Poisson arrivals at 50 %, 80 % and 95 % of that capacity.
+    Reports served CSEU/s and p50/p99 latency (arrival to result) per load, with each request's
+    colourings capped per batch (slot_colourings) so that small requests share the batches of large
+    ones; at the highest load the same arrivals also run first come, first served without the cap,
+    which shows the head-of-line blocking the cap relieves (latencies of the smaller and larger
+    halves of the requests reported apart). The 80 % figures are the headline latencies."""
+    import numpy as np
     import torch
 
     import inputs
@@ -522,10 +537,12 @@ def serving_leg(args):
     from paper_1804_09764_amd.serving import GpuExecutor, Server, latency_summary
 
     dev = torch.device("cuda:0")
-    pool = []
+    mix = SERVE_MIXES[args.serve_mix]
+    pool, pool_desc = [], []
     for scale, ef, seed in SERVE_POOL:
         rp, col = inputs.rmat_graph_gpu(scale, ef, seed, device=dev)
         pool.append(cc.Graph(rp, col, trust=True))
+        pool_desc.append((scale, ef, seed))
     units_cache = {}
 
     def units(r):
@@ -536,47 +553,75 @@ def serving_leg(args):
 
     ex = GpuExecutor(pool, seed_base=args.seed, n_streams=2)
     budget = int(args.serve_budget_gb * 1e9)
+    nreq = args.serve_requests
+
+    def reqs_at(rate):
+        return make_requests(nreq, pool_desc, seed=9, rate=rate, b_range=mix["b_range"], max_scale=mix["max_scale"])
 
     def progress(r):
-        print(f"[bench] served request {r.rid}: graph {r.graph_id} k={r.k} B={r.B} {r.status} "
-              f"latency {r.latency:.2f}s", file=sys.stderr, flush=True)
+        if r.rid % 20 == 19:
+            print(f"[bench] served request {r.rid}: k={r.k} B={r.B} {r.status} latency {r.latency:.2f}s",
+                  file=sys.stderr, flush=True)
+
+    def serve(reqs, cap):
+        srv = Server(ex, budget, max_inflight=2, slot_colourings=cap, on_complete=progress)
+        t0 = time.perf_counter()
+        srv.run(reqs)
+        return srv, time.perf_counter() - t0
+
+    def summary(reqs, srv, wall, rate):
+        lat = latency_summary(reqs)
+        served = sum(units(r) for r in reqs if r.status == "done")
+        work = np.array([units(r) for r in reqs])
+        small = work <= np.median(work)
+        ls = latency_summary([r for r, m in zip(reqs, small) if m])
+        lb = latency_summary([r for r, m in zip(reqs, small) if not m])
+        return {"arrival_rate_per_s": rate, "requests": len(reqs), "failed": sum(r.status != "done" for r in reqs),
+                "wall_s": wall, "throughput_CSEU_per_s": served / wall,
+                "p50_latency_s": lat.get("p50_s"), "p99_latency_s": lat.get("p99_s"), "mean_latency_s": lat.get("mean_s"),
+                "smaller_half_p50_s": ls.get("p50_s"), "smaller_half_p99_s": ls.get("p99_s"),
+                "larger_half_p50_s": lb.get("p50_s"), "larger_half_p99_s": lb.get("p99_s"),
+                "batches": srv.stats.batches,
+                "mean_colourings_per_batch": (sum(srv.stats.batch_sizes) / max(1, srv.stats.batches)),
+                "max_inflight_batches": srv.stats.max_inflight_batches,
+                "max_inflight_GB": srv.stats.max_inflight_bytes / 1e9}
 
     # warm up (plans, allocator) on a few small requests
-    warm = make_requests(4, len(pool), seed=1, rate=0, b_range=(2, 4))
+    warm = make_requests(4, pool_desc, seed=1, rate=0, b_range=(2, 4), max_scale=18)
     Server(ex, budget, max_inflight=2).run(warm)
     torch.cuda.synchronize()
-    cap_reqs = make_requests(args.serve_capacity_requests, len(pool), seed=2, rate=0)
-    srv = Server(ex, budget, max_inflight=2, on_complete=progress)
-    t0 = time.perf_counter()
-    srv.run(cap_reqs)
-    makespan = time.perf_counter() - t0
+    cap_reqs = reqs_at(0)
+    srv, makespan = serve(cap_reqs, args.serve_cap)
     capacity = len(cap_reqs) / makespan
     cap_units = sum(units(r) for r in cap_reqs if r.status == "done")
-    print(f"[bench] serving capacity {capacity:.3f} requests/s", file=sys.stderr, flush=True)
+    print(f"[bench] serving capacity {capacity:.3f} requests/s ({makespan:.1f} s for {len(cap_reqs)})",
+          file=sys.stderr, flush=True)
     loads = {}
     for load in args.serve_loads:
         rate = load * capacity
-        reqs = make_requests(args.serve_requests, len(pool), seed=9, rate=rate)
-        print(f"[bench] Poisson arrivals at {load:.2f} x capacity = {rate:.3f}/s", file=sys.stderr, flush=True)
-        srv2 = Server(ex, budget, max_inflight=2, on_complete=progress)
-        t0 = time.perf_counter()
-        srv2.run(reqs)
-        wall = time.perf_counter() - t0
-        lat = latency_summary(reqs)
-        served = sum(units(r) for r in reqs if r.status == "done")
-        loads[f"{load:.2f}"] = {
-            "arrival_rate_per_s": rate, "requests": len(reqs), "failed": sum(r.status != "done" for r in reqs),
-            "wall_s": wall, "throughput_CSEU_per_s": served / wall,
-            "p50_latency_s": lat.get("p50_s"), "p99_latency_s": lat.get("p99_s"), "mean_latency_s": lat.get("mean_s"),
-            "batches": srv2.stats.batches,
-            "mean_colourings_per_batch": (sum(srv2.stats.batch_sizes) / max(1, srv2.stats.batches)),
-            "max_inflight_batches": srv2.stats.max_inflight_batches,
-            "max_inflight_GB": srv2.stats.max_inflight_bytes / 1e9}
+        reqs = reqs_at(rate)
+        srv, wall = serve(reqs, args.serve_cap)
+        loads[f"{load:.2f}"] = summary(reqs, srv, wall, rate)
+        print(f"[bench] Poisson arrivals at {load:.2f} x capacity = {rate:.3f}/s: {wall:.1f} s, "
+              f"p50 {loads[f'{load:.2f}']['p50_latency_s']:.2f} s p99 {loads[f'{load:.2f}']['p99_latency_s']:.2f} s",
+              file=sys.stderr, flush=True)
+    fifo = None
+    if args.serve_fifo_load > 0:
+        rate = args.serve_fifo_load * capacity
+        reqs = reqs_at(rate)
+        srv, wall = serve(reqs, 0)
+        fifo = summary(reqs, srv, wall, rate)
+        fifo["load"] = args.serve_fifo_load
+        print(f"[bench] first come first served, no cap, at {args.serve_fifo_load:.2f} x capacity: "
+              f"p50 {fifo['p50_latency_s']:.2f} s p99 {fifo['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
     head = loads.get("0.80") or next(iter(loads.values()))
-    return {"workload": "Poisson requests over 16 resident R-MAT graphs (scale 16-22, edge factor 8-32), "
-                        "Pruefer trees k in 5..12, 8..128 colourings",
+    return {"workload": f"Poisson requests over 16 resident R-MAT graphs (scale 16-22, edge factor 8-32), "
+                        f"Pruefer trees k in 5..12; mix '{args.serve_mix}': graphs of scale <= {mix['max_scale']}, "
+                        f"{mix['b_range'][0]}..{mix['b_range'][1]} colourings per request; the same {nreq} "
+                        f"requests (seed 9) for the capacity and every load",
+            "slot_colourings": args.serve_cap,
             "capacity_requests_per_s": capacity, "capacity_CSEU_per_s": cap_units / makespan,
-            "memory_budget_GB": budget / 1e9, "loads": loads,
+            "memory_budget_GB": budget / 1e9, "loads": loads, "fifo_uncapped": fifo,
             "p50_latency_s": head["p50_latency_s"], "p99_latency_s": head["p99_latency_s"],
             "throughput_CSEU_per_s": head["throughput_CSEU_per_s"]}
 
@@ -657,12 +702,18 @@ def main():
                     help="run only the plain-vs-batched comparison (for profiling its kernels)")
     ap.add_argument("--progress", type=int, default=1,
                     help="print a line after each timed step (synchronises between steps)")
-    ap.add_argument("--serve-requests", type=int, default=12, help="requests per arrival rate")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests of the capacity run and of each arrival rate (the same requests)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95],
                     help="Poisson arrival rates as fractions of the measured capacity")
-    ap.add_argument("--serve-capacity-requests", type=int, default=10)
+    ap.add_argument("--serve-mix", default="light", choices=sorted(SERVE_MIXES))
+    ap.add_argument("--serve-cap", type=int, default=16,
+                    help="colourings of one request per batch (0: as many as fit)")
+    ap.add_argument("--serve-fifo-load", type=float, default=0.95,
+                    help="also run this load without the cap, first come first served (0: skip)")
+    ap.add_argument("--only-serving", action="store_true", help="run only the serving leg")
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--summarize-pmc", action="store_true")
@@ -691,6 +742,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.only_serving:
+        print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return 0
     if args.only_batched:
         # the batched leg alone (for profiling its kernels); not the benchmark line
         print(json.dumps({"batched": batched_vs_plain(args)}), flush=True)

@@ -11,6 +11,10 @@ colourings (Algorithm 1's outer loop). Requests arrive over time; the server
     packs admissible slots of the oldest waiting requests (first come, first served, several
     requests per batch) into one batch and launches it on its own stream, so that newly arrived
     requests join while others are still running and their work overlaps on the device;
+  * optionally caps the colourings one request puts into one batch (`slot_colourings`): a large
+    request then advances a slice per batch and the requests behind it share every batch, instead
+    of waiting behind it (head-of-line blocking); memory admission stays first come, first
+    served (a request that does not fit stops the scan);
   * completes a request when all of its colourings are back, and records its latency
     (arrival to completion) and estimate.
 
@@ -95,12 +99,14 @@ class Stats:
 
 class Server:
     def __init__(self, executor: Executor, memory_budget: int, max_inflight: int = 2,
-                 max_colourings_per_batch: int = 256, clock=time.perf_counter, on_complete=None):
+                 max_colourings_per_batch: int = 256, clock=time.perf_counter, on_complete=None,
+                 slot_colourings: int = 0):
         self.ex = executor
         self.on_complete = on_complete
         self.budget = int(memory_budget)
         self.max_inflight = max_inflight
         self.max_slots = max_colourings_per_batch
+        self.slot_cap = int(slot_colourings)  # 0: a request takes as many colourings as fit
         self.clock = clock
         self.queue: deque[Request] = deque()
         self.inflight: list = []  # (handle, slots, nbytes)
@@ -135,14 +141,18 @@ class Server:
     # -- device side -------------------------------------------------------------------------
     def _form_batch(self) -> list[Slot]:
         """Pack admissible colourings of the oldest waiting requests into one batch. Requests are
-        served first come, first served: a request that cannot be fully admitted stops the scan,
-        so later requests never overtake it."""
+        served first come, first served: a request whose colourings do not fit in the memory left
+        stops the scan, so later requests never overtake it; a request that reached its per-batch
+        cap (`slot_colourings`) lets the next ones in."""
         slots: list[Slot] = []
         free = self.budget - self.inflight_bytes
         left = self.max_slots
         for req in self.queue:
             per = self.ex.slot_bytes(req, 1)
-            cnt = int(min(req.B - req.next_colouring, left, free // per))
+            want = min(req.B - req.next_colouring, left)
+            if self.slot_cap > 0:
+                want = min(want, self.slot_cap)
+            cnt = int(min(want, free // per))
             # a slot's memory need not be exactly linear in its colourings: shrink until it fits
             while cnt > 0 and self.ex.slot_bytes(req, cnt) > free:
                 cnt = cnt - max(1, cnt // 8)
@@ -153,7 +163,7 @@ class Server:
                 req.status = "running"
                 left -= cnt
                 free -= need
-            if req.next_colouring < req.B or left == 0:
+            if cnt < want or left == 0:
                 break
         self.queue = deque(r for r in self.queue if r.next_colouring < r.B)
         return slots
