@@ -252,6 +252,21 @@ cc_status cc_count(const cc_plan* plan, const cc_graph* g, const uint8_t* colour
                    void* ws_dev, size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): cc_count with the workspace taken from a fixed array of
+ * CC_NOALLOC_SCRATCH_BYTES that the library holds in device memory, one per GPU, until the process
+ * ends. Same arguments and results as cc_count (bit for bit: the same kernels in the same order);
+ * no workspace argument. Allocates nothing (no hipMalloc, hipFree or allocating library call);
+ * the plan's profiling must be off. CC_ENOSPC with a message when cc_count_workspace_bytes for this
+ * plan and graph exceeds CC_NOALLOC_SCRATCH_BYTES, CC_EINVAL when the graph's device is not the
+ * current one. All calls on one GPU share the array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.
+ */
+#define CC_NOALLOC_SCRATCH_BYTES (128u << 20)  /* 128 MiB per GPU */
+cc_status cc_count_noalloc(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
+                           double* X_dev, double* vertex_dev, void* stream);
+
+/*
  * Inspection of one step of the dynamic program (Section 2.1, Eq. 1: the table C(., T_i, .) of a
  * split is computed from the tables of its active part T_i' and passive part T_i'' alone), so that
  * a caller can check any single split at sizes where the whole count cannot be recomputed on the

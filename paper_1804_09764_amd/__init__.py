@@ -88,7 +88,7 @@ EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split
            "cc_plan_bind_device", "cc_plan_destroy", "cc_entry_order", "cc_plan_split_maps",
            "cc_plan_constants_get", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
-           "cc_count_inspect", "cc_plan_table_get", "cc_count_projection",
+           "cc_count_inspect", "cc_plan_table_get", "cc_count_projection", "cc_count_noalloc",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
            "cc_multi_create", "cc_multi_info_get", "cc_multi_step_get", "cc_multi_destroy",
            "cc_count_packed_multi_workspace_bytes",
@@ -127,6 +127,7 @@ def lib() -> ctypes.CDLL:
         "cc_count_inspect": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P]),
         "cc_plan_table_get": (ctypes.c_int, [P, P, I32, ctypes.POINTER(_TableDesc)]),
         "cc_count_projection": (ctypes.c_int, [P, P, P, I32]),
+        "cc_count_noalloc": (ctypes.c_int, [P, P, P, I32, P, P, P]),
         "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_stream_check": (ctypes.c_int, [P]),
@@ -361,6 +362,29 @@ def count(plan: Plan, graph: Graph, colours, per_vertex: bool = False, workspace
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dev_ptr(X, torch.float64, "X"),
                           _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
     return (X, V) if per_vertex else X
+
+
+CC_NOALLOC_SCRATCH_BYTES = 128 << 20  # the fixed workspace of cc_count_noalloc, per GPU
+
+
+def count_noalloc(plan: Plan, graph: Graph, colours, out, vertex_out=None, stream=None):
+    """cc_count_noalloc: X[b] for each colouring row of `colours` into the caller's `out` (float64,
+    B) and optionally `vertex_out` (float64, [B, n]), with the library's fixed workspace: no device
+    memory is allocated by this call."""
+    import torch
+    if colours.dim() == 1:
+        colours = colours.view(1, -1)
+    B = colours.shape[0]
+    if colours.shape[1] != graph.n:
+        raise ValueError("colours must be [B, n]")
+    if out.numel() < B:
+        raise ValueError("out must hold B doubles")
+    if vertex_out is not None and vertex_out.numel() < B * graph.n:
+        raise ValueError("vertex_out must hold B * n doubles")
+    _check(lib().cc_count_noalloc(plan.handle, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B,
+                                  _dev_ptr(out, torch.float64, "out"), _dev_ptr(vertex_out, torch.float64, "vertex_out"),
+                                  _stream(stream)))
+    return out
 
 
 def count_inspect(plan: Plan, graph: Graph, colours, last: int, workspace: Workspace | None = None,

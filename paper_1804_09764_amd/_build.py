@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcc.so")
-SOURCES = ["cc_kernels.hip", "cc_packed.hip", "cc_plan.cpp", "cc_api.cpp", "cc_multi.cpp", "cc_batch.cpp"]
+SOURCES = ["cc_kernels.hip", "cc_packed.hip", "cc_noalloc.hip", "cc_plan.cpp", "cc_api.cpp", "cc_multi.cpp", "cc_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept out of every HIP build.
