@@ -41,6 +41,8 @@ WORKLOADS = {
     "rmat20-ef16-u12": dict(scale=20, ef=16, gseed=1, k=12, tseed=12, B=1, trust=False),
     "rmat23-ef256-u12": dict(scale=23, ef=256, gseed=3, k=12, tseed=12, B=4, trust=True),
     "rmat20-ef16-u15": dict(scale=20, ef=16, gseed=1, k=15, tseed=15, B=1, trust=False),
+    # a 15-vertex tree whose live tables exceed HBM (counted with --only-budget)
+    "rmat22-ef16-u15": dict(scale=22, ef=16, gseed=1, k=15, tseed=15, B=1, trust=True),
 }
 DEFAULT_WORKLOAD = "rmat23-ef256-u12"
 
@@ -132,6 +134,22 @@ def method_bytes_packed(k, s, a, p, n, nnz, B):
     return b
 
 
+def loaded_bytes_projected(k, s, a, p, n, nnz, classes):
+    """loaded_bytes for a split on projected passive rows (classes colour classes per pass): per CSR
+    entry the neighbour's colour and column and, for the fraction (k-1)/k of neighbours whose colour
+    differs from the row's, its projected row (C(k-2, p-1) entries padded to whole 128-byte
+    lines); per vertex the same as loaded_bytes; plus the copies: every pass reads the table once
+    and every vertex writes one projected row per colour other than its own."""
+    Wp, Wa, Ws = widths(k, s, a, p)
+    wn_pad = (math.comb(k - 2, p - 1) + 15) // 16 * 16
+    wp_pad = (Wp + 15) // 16 * 16
+    passes = -(-k // classes)
+    b = 5 * nnz + 8 * (n + 1) + n + 8 * n * Ws + (8 * n * Wa if a >= 2 else 0)
+    b += 8 * wn_pad * nnz * (k - 1) / k
+    b += passes * 8 * n * wp_pad + (k - 1) * 8 * n * wn_pad
+    return b
+
+
 def loaded_bytes(k, s, a, p, n, nnz):
     """Algorithmic bytes of one split launch: what its loads and stores must move from HBM at the
     128-byte line granularity of the layout. Per CSR entry: the neighbour's colour (1 B, from the
@@ -170,7 +188,7 @@ def packed_kernel_split(k, s, a, p):
 def load_traffic(workload: str, split_index: int):
     """HBM traffic per launch (GB) of the dominant kernel from committed rocprofv3 counters, or None
     if they were taken on another kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_split_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -225,7 +243,17 @@ def cpu_baseline(row_ptr, col, T, target_s=15.0):
     while secs < target_s / 2 and m < n:
         m = min(n, int(m * max(2.0, min(8.0, target_s / max(secs, 1e-3)))))
         units, secs, m = run(m)
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": units / secs, "unit": "CSEU/s", "cores": oracle.threads(), "kind": "oracle",
+            "cpu_model": cpu_model, "host_cpus_visible": os.cpu_count(),
             "sample": f"{m} uniformly sampled centre vertices with their neighbour lists, every split of the "
                       f"reference partition, random integer tables (passive rows: 65536, indexed by neighbour id "
                       f"mod 65536); {units:.3e} CSEU in {secs:.1f} s"}
@@ -266,6 +294,12 @@ def bench(args):
     proj = cc.count_projection(P, G)
     print(f"[bench] plan root={P.info.root} splits={P.splits} workspace={ws_bytes / 1e9:.2f} GB "
           f"graph={G.info} projected classes per pass={proj}", file=sys.stderr, flush=True)
+    if args.dispatch_map:
+        # the dominant split: the one whose passive rows are the widest (ties: the later split)
+        widths_p = [math.comb(k - 1, p - 1) if p >= 2 else 0 for (_, _, p) in P.splits]
+        dom_split = max(range(len(widths_p)), key=lambda i: (widths_p[i], i))
+        json.dump({"sequence": dispatch_sequence(P, G, proj), "dominant_split": dom_split},
+                  open(args.dispatch_map, "w"))
 
     packed = args.path in ("packed", "auto")
     pack = B
@@ -319,7 +353,12 @@ def bench(args):
     avg_ms = gather_ms[dom] / max(1, launches[dom])
     dom_packed = packed and packed_kernel_split(k, s, a, p)
     alg = method_bytes_packed(k, s, a, p, n, nnz, pack) if dom_packed else method_bytes(k, s, a, p, n, nnz)
-    lines = loaded_bytes_packed(k, s, a, p, n, nnz, pack) if dom_packed else loaded_bytes(k, s, a, p, n, nnz)
+    if dom_packed:
+        lines = loaded_bytes_packed(k, s, a, p, n, nnz, pack)
+    elif proj[dom] > 0:
+        lines = loaded_bytes_projected(k, s, a, p, n, nnz, proj[dom])
+    else:
+        lines = loaded_bytes(k, s, a, p, n, nnz)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     traffic = None if dom_packed else load_traffic(args.workload, dom)
     per_split = [{"s": S, "a": A, "p": Pp, "gather_ms": round(float(g) / max(1, c), 4),
@@ -353,20 +392,26 @@ def bench(args):
                                      "read for a 1 GiB device copy. These count L2-to-fabric requests, "
                                      "Infinity Cache hits included: an upper bound of the DRAM bytes, not "
                                      "a DRAM measurement",
-                     "kernel": f"{'k_psplit' if dom_packed else 'k_split'} split {dom} (s={s}, a={a}, p={p})",
+                     "kernel": (f"k_psplit split {dom} (s={s}, a={a}, p={p})" if dom_packed else
+                                f"k_project + k_split split {dom} (s={s}, a={a}, p={p}), projected rows, "
+                                f"{proj[dom]} colour classes per pass" if proj[dom] > 0 else
+                                f"k_split split {dom} (s={s}, a={a}, p={p})"),
                      "avg_launch_ms": avg_ms,
                      "algorithmic_bytes_per_launch": alg,
                      "algorithmic_bytes": "method bytes: only the passive entries the combine uses "
                                           "(bench.py method_bytes)",
                      "line_bytes_per_launch": lines,
                      "line_GBps": lines / (avg_ms * 1e-3) / 1e9,
-                     "line_bytes": "the 128-byte lines holding a needed entry (bench.py loaded_bytes)",
+                     "line_bytes": "the 128-byte lines holding a needed entry, plus the row copies of a "
+                                   "projected split (bench.py loaded_bytes, loaded_bytes_projected)",
                      "compulsory_bytes_per_launch": split_bytes(k, s, a, p, n, nnz),
                      "traffic_GBps": (traffic / (avg_ms * 1e-3)) if traffic else None,
                      "traffic_over_method": (traffic * 1e9 / alg) if traffic else None},
         "splits": per_split,
         "X_last": [float(x) for x in Xh],
     }
+    if args.budget_frac > 0:
+        out["budget"] = budget_leg(P, G, k, args, cc.count_workspace_bytes(P, G), ws)
     if not args.no_cpu_baseline:
         row_ptr, col = rp_d.cpu().numpy(), col_d.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(row_ptr, col, T, target_s=args.cpu_seconds)
@@ -383,6 +428,84 @@ def bench(args):
         out["p50_latency_s"] = out["serving"]["p50_latency_s"]
         out["p99_latency_s"] = out["serving"]["p99_latency_s"]
     return out
+
+
+def beyond_hbm(args):
+    """One colouring of a workload whose plain count does not fit in HBM, counted within
+    --budget-gb of device workspace (cc_count_budget), twice at two budgets: the counts must agree
+    (bit for bit when the budgets park the same tables and project alike, else within 1e-12)."""
+    import torch
+
+    import inputs
+    import paper_1804_09764_amd as cc
+    W = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    rp_d, col_d = inputs.rmat_graph_gpu(W["scale"], W["ef"], W["gseed"], device=dev)
+    G = cc.Graph(rp_d, col_d, trust=W["trust"])
+    P = cc.Plan(inputs.pruefer_tree(W["k"], W["tseed"]))
+    print(f"[bench] graph n={G.n} nnz={G.nnz} in {time.time() - t0:.1f}s; plain workspace "
+          f"{cc.count_workspace_bytes(P, G) / 1e9:.1f} GB, free {torch.cuda.mem_get_info(dev)[0] / 1e9:.1f} GB",
+          file=sys.stderr, flush=True)
+    C = cc.colour(G, W["k"], seed=args.seed, first_iter=0, B=1)
+    out = {"workload": args.workload, "n": G.n, "nnz": G.nnz,
+           "plain_workspace_GB": cc.count_workspace_bytes(P, G) / 1e9, "runs": []}
+    ws = cc.Workspace()
+    Xs = []
+    budgets = (args.budget_gb, args.budget_gb * 0.85)
+    infos = [cc.count_budget_plan(P, G, int(gb * 1e9)) for gb in budgets]
+    # one pinned host buffer for both runs (the larger need)
+    host = torch.empty(max(max(i["host_bytes"] for i in infos), 1), dtype=torch.uint8, pin_memory=True)
+    for gb, info in zip(budgets, infos):
+        X = torch.empty(1, dtype=torch.float64, device=dev)
+        cc.count_budget(P, G, C, int(gb * 1e9), workspace=ws, host=host, out=X)  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cc.count_budget(P, G, C, int(gb * 1e9), workspace=ws, host=host, out=X)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3
+        Xs.append(float(X.cpu()[0]))
+        out["runs"].append({"budget_GB": gb, "workspace_GB": info["workspace_bytes"] / 1e9,
+                            "host_GB": info["host_bytes"] / 1e9, "parked_tables": info["parked_tables"],
+                            "proj_classes": info["proj_classes"], "arena_columns": info["arena_columns"],
+                            "unbounded_columns": info["unbounded_columns"], "ms": ms, "X": Xs[-1],
+                            "CSEU_per_s": float(G.nnz) * P.info.units_per_edge / (ms * 1e-3)})
+        print(f"[bench] budget {gb:.0f} GB: {out['runs'][-1]}", file=sys.stderr, flush=True)
+    out["agree"] = bool(Xs[0] == Xs[1] or abs(Xs[0] - Xs[1]) <= 1e-12 * max(Xs))
+    return out
+
+
+def budget_leg(P, G, k, args, full_bytes, ws):
+    """One colouring of the headline workload counted within a device budget of budget_frac of the
+    plain count's workspace (cc_count_budget: tables idle across the peak wait in pinned host
+    memory), against the plain count of the same colouring: time, arenas, bytes parked, and
+    whether the counts are bit-identical."""
+    import torch
+
+    import paper_1804_09764_amd as cc
+    dev = torch.device("cuda:0")
+    budget = int(full_bytes * args.budget_frac)
+    try:
+        info = cc.count_budget_plan(P, G, budget)
+    except cc.CCError as e:
+        return {"budget_GB": budget / 1e9, "fits": False, "error": str(e)}
+    C = cc.colour(G, k, seed=args.seed, first_iter=10 ** 6, B=1)
+    host = torch.empty(max(info["host_bytes"], 1), dtype=torch.uint8, pin_memory=True)
+    X0 = torch.empty(1, dtype=torch.float64, device=dev)
+    X1 = torch.empty(1, dtype=torch.float64, device=dev)
+    res = {}
+    for name, fn in (("plain", lambda: cc.count(P, G, C, workspace=ws, out=X0)),
+                     ("budget", lambda: cc.count_budget(P, G, C, budget, workspace=ws, host=host, out=X1))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) * 1e3
+    return {"budget_GB": budget / 1e9, "fits": True, "workspace_GB": info["workspace_bytes"] / 1e9,
+            "plain_workspace_GB": full_bytes / 1e9, "parked_tables": info["parked_tables"],
+            "host_GB": info["host_bytes"] / 1e9, "arena_columns": info["arena_columns"],
+            "unbounded_columns": info["unbounded_columns"], "plain_ms": res["plain"], "budget_ms": res["budget"],
+            "bit_identical": bool(torch.equal(X0, X1))}
 
 
 def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
@@ -404,6 +527,8 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
     import inputs
     import paper_1804_09764_amd as cc
 
+    from paper_1804_09764_amd import autotune
+
     dev = torch.device("cuda:0")
     rp_d, col_d = inputs.rmat_graph_gpu(18, 16, 2, device=dev)
     n, nnz = rp_d.numel() - 1, col_d.numel()
@@ -412,6 +537,14 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
     plans = [cc.Plan(T) for T in trees]
     B = 64
     C = cc.colour(G, 7, seed=args.seed, first_iter=0, B=B)
+    # the batched path's degree split and tile row, chosen by measurement before timing
+    t0 = time.perf_counter()
+    rec = autotune.tune_multi(plans, rp_d, col_d, B=B, seed=args.seed, repeats=2, trust=True)
+    tune_s = time.perf_counter() - t0
+    Gt = cc.Graph(rp_d, col_d, hub_threshold=rec.hub_threshold, chunk=rec.chunk, packed_tile=rec.packed_tile,
+                  trust=True)
+    print(f"[bench] batched autotune ({tune_s:.1f} s): tau={rec.hub_threshold} c={rec.chunk} "
+          f"tile={rec.packed_tile} {rec.ms:.1f} ms (default {rec.default_ms:.1f} ms)", file=sys.stderr, flush=True)
     units = float(nnz) * sum(p.info.units_per_edge for p in plans) * B
     ws = cc.Workspace()
     Xp = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
@@ -425,14 +558,20 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
 
     def packed():
         for t, P in enumerate(plans):
-            cc.count_packed(P, G, C, workspace=wsk, out=Xk[t])
+            cc.count_packed(P, Gt, C, workspace=wsk, out=Xk[t])
 
     multi = cc.Multi(plans)
     Xm = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
     wsm = cc.Workspace()
 
     def shared():
-        multi.count(G, C, workspace=wsm, out=Xm)
+        multi.count(Gt, C, workspace=wsm, out=Xm)
+
+    Xq = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
+    wsq = cc.Workspace()
+
+    def persistent_multi():
+        multi.count(Gt, C, workspace=wsq, out=Xq, persistent=True)
 
     Xb = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
     inst = [(P, G, C[b], Xb[t, b:b + 1], None) for t, P in enumerate(plans) for b in range(B)]
@@ -440,7 +579,8 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
     levels = cc.Batch(inst, levels=True)
     wsb = cc.Workspace()
     res = {}
-    for name, fn in (("plain", plain), ("batched", shared), ("packed_per_tree", packed),
+    for name, fn in (("plain", plain), ("batched", shared), ("batched_persistent", persistent_multi),
+                     ("packed_per_tree", packed),
                      ("instances_persistent", lambda: persistent.run(wsb)), ("instances_levels", lambda: levels.run(wsb))):
         fn()
         torch.cuda.synchronize()
@@ -469,9 +609,18 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
             "batched": {"value": units / res["batched"], "ms": res["batched"] * 1e3,
                         "speedup_vs_plain": res["plain"] / res["batched"],
                         "matches_plain": matches(Xm.cpu().numpy()), "above_2_53": int((~small).sum()),
-                        "launch": "one packed multi-template count: 64 colourings per table row, "
-                                  "equal sub-template tables shared by the 11 trees",
-                        "splits_run": multi.info["steps"], "splits_total": multi.info["splits"]},
+                        "launch": "one packed multi-template count, one launch per split: 64 colourings per "
+                                  "table row, equal sub-template tables shared by the 11 trees",
+                        "splits_run": multi.info["steps"], "splits_total": multi.info["splits"],
+                        "autotuned": {"hub_threshold": rec.hub_threshold, "chunk": rec.chunk,
+                                      "packed_tile": rec.packed_tile, "ms": rec.ms, "default_ms": rec.default_ms,
+                                      "candidates": len(rec.timings), "tuning_s": tune_s}},
+            "batched_persistent": {"value": units / res["batched_persistent"], "ms": res["batched_persistent"] * 1e3,
+                                   "speedup_vs_plain": res["plain"] / res["batched_persistent"],
+                                   "equal_to_batched": bool(torch.equal(Xq, Xm)),
+                                   "launch": "the same count in one persistent cooperative launch over (split, "
+                                             "task or cut row, colouring tile) items, dependency levels separated "
+                                             "by a device-wide barrier"},
             "packed_per_tree": {"value": units / res["packed_per_tree"], "ms": res["packed_per_tree"] * 1e3,
                                 "matches_plain": matches(Xk.cpu().numpy()),
                                 "launch": "one packed count per tree"},
@@ -490,15 +639,19 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
 SERVE_POOL = [(16 + (i % 7), (8, 16, 32)[i % 3], 100 + i) for i in range(16)]  # (scale, edge factor, seed)
 # request mixes: "full" draws every graph of the pool and 8..128 colourings per request; "light"
 # keeps k in 5..12 but draws only the graphs of scale <= 20 and 8..16 colourings, so that 100 or
-# more requests per arrival rate fit in the benchmark's time
-SERVE_MIXES = {"full": dict(max_scale=22, b_range=(8, 128)), "light": dict(max_scale=20, b_range=(8, 16))}
+# more requests per arrival rate fit in the benchmark's time; "bench" is "light" with one request
+# in ten a large one of 64..128 colourings (the head-of-line case)
+SERVE_MIXES = {"full": dict(max_scale=22, b_range=(8, 128), large=0.0),
+               "light": dict(max_scale=20, b_range=(8, 16), large=0.0),
+               "bench": dict(max_scale=20, b_range=(8, 16), large=0.1)}
+LARGE_B = (64, 128)  # colourings of the occasional large request of the "bench" mix
 
 
-def make_requests(n, pool, seed, rate, k_range=(5, 12), b_range=(8, 128), max_scale=22, t0=0.0):
+def make_requests(n, pool, seed, rate, k_range=(5, 12), b_range=(8, 128), max_scale=22, large=0.0, t0=0.0):
     """n requests with Poisson arrivals at `rate` per second (all at t0 if rate is 0): a graph
     uniform over the pool's graphs of scale <= max_scale, a Pruefer tree with k uniform in k_range
-    (seeded by the request id), B uniform in b_range colourings. The same seed gives the same
-    requests whatever the rate."""
+    (seeded by the request id), B uniform in b_range colourings, or with probability `large` in
+    LARGE_B. The same seed gives the same requests whatever the rate."""
     import numpy as np
 
     import inputs
@@ -513,6 +666,8 @@ def make_requests(n, pool, seed, rate, k_range=(5, 12), b_range=(8, 128), max_sc
             t += arr.exponential(1.0 / rate)
         k = int(rng.integers(k_range[0], k_range[1] + 1))
         B = int(rng.integers(b_range[0], b_range[1] + 1))
+        if rng.random() < large:
+            B = int(rng.integers(LARGE_B[0], LARGE_B[1] + 1))
         gid = gids[int(rng.integers(0, len(gids)))]
         rid = seed * 100000 + i
         out.append(Request(rid=rid, graph_id=gid, tree_edges=inputs.pruefer_tree(k, rid), B=B, seed=rid, arrival=t))
@@ -556,7 +711,8 @@ def serving_leg(args):
     nreq = args.serve_requests
 
     def reqs_at(rate):
-        return make_requests(nreq, pool_desc, seed=9, rate=rate, b_range=mix["b_range"], max_scale=mix["max_scale"])
+        return make_requests(nreq, pool_desc, seed=9, rate=rate, b_range=mix["b_range"], max_scale=mix["max_scale"],
+                             large=mix["large"])
 
     def progress(r):
         if r.rid % 20 == 19:
@@ -617,8 +773,10 @@ def serving_leg(args):
     head = loads.get("0.80") or next(iter(loads.values()))
     return {"workload": f"Poisson requests over 16 resident R-MAT graphs (scale 16-22, edge factor 8-32), "
                         f"Pruefer trees k in 5..12; mix '{args.serve_mix}': graphs of scale <= {mix['max_scale']}, "
-                        f"{mix['b_range'][0]}..{mix['b_range'][1]} colourings per request; the same {nreq} "
-                        f"requests (seed 9) for the capacity and every load",
+                        f"{mix['b_range'][0]}..{mix['b_range'][1]} colourings per request"
+                        + (f", one request in {round(1 / mix['large'])} with {LARGE_B[0]}..{LARGE_B[1]}"
+                           if mix["large"] > 0 else "")
+                        + f"; the same {nreq} requests (seed 9) for the capacity and every load",
             "slot_colourings": args.serve_cap,
             "capacity_requests_per_s": capacity, "capacity_CSEU_per_s": cap_units / makespan,
             "memory_budget_GB": budget / 1e9, "loads": loads, "fifo_uncapped": fifo,
@@ -626,10 +784,37 @@ def serving_leg(args):
             "throughput_CSEU_per_s": head["throughput_CSEU_per_s"]}
 
 
+COUNT_KERNELS = ("k_edge_colours", "k_project", "k_split", "k_hub_finish", "k_reduce_blocks", "k_reduce_final")
+
+
+def dispatch_sequence(P, G, proj):
+    """The kernels cc_count dispatches for one colouring, in order, each with the split it belongs
+    to (-1: none): the neighbour-colour gather; per split either its task kernel or, when projected,
+    a copy and a task kernel per pass of colour classes, then the cut-row finish; the root sum."""
+    seq = [("k_edge_colours", -1)]
+    tasks = G.info["n_chunks"] + G.info["n_light"] > 0
+    for i in range(P.info.n_splits):
+        if proj[i] > 0:
+            passes = -(-P.k // proj[i])
+            per = -(-P.k // passes)
+            for c0 in range(0, P.k, per):
+                seq.append(("k_project", i))
+                if tasks:
+                    seq.append(("k_split", i))
+        elif tasks:
+            seq.append(("k_split", i))
+        if G.info["n_hubs"] > 0:
+            seq.append(("k_hub_finish", i))
+    seq += [("k_reduce_blocks", -1), ("k_reduce_final", -1)]
+    return seq
+
+
 def summarize_pmc(args):
     """rocprofv3 --pmc output (counter_collection.csv of a FETCH_SIZE run and of a WRITE_SIZE run)
-    -> profiles/k_split_<workload>_pmc.json: the dominant split kernel's bytes per launch, scaled
-    by what the same counters read for a plain copy of known size."""
+    -> gpurun_out/pmc_<workload>.json: the bytes one colouring's dominant split moves (all of its
+    kernels: row copies, passes, cut-row finish), scaled by what the same counters read for a plain
+    copy of known size. Dispatches are matched to splits by cc_count's launch sequence
+    (dispatch_sequence, written by the profiled bench run with --dispatch-map)."""
     def rows(d):
         out = []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
@@ -637,44 +822,46 @@ def summarize_pmc(args):
                 out += list(csv.DictReader(fh))
         return out
 
-    def per_kernel(rs, counter):
-        d = {}
+    def dispatches(rs, counter):
+        out = []
         for r in sorted(rs, key=lambda r: int(r.get("Dispatch_Id", 0))):
-            if r.get("Counter_Name") != counter:
-                continue
-            d.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return d
+            if r.get("Counter_Name") == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return out
 
-    fetch = per_kernel(rows(args.fetch_dir), "FETCH_SIZE")
-    write = per_kernel(rows(args.write_dir), "WRITE_SIZE")
-    copy_bytes = args.copy_bytes
+    dm = json.load(open(args.dispatch_map))
+    seq = [tuple(x) for x in dm["sequence"]]
+    dom = dm["dominant_split"]
 
-    def copy_kib(d):
-        # the calibration copies (bench.py --copy-calibration) are the first three device-to-device
-        # copy dispatches of the run
-        for name, v in d.items():
-            if "copybuffer" in name.lower() and len(v) >= 3:
-                return sorted(v[:3])[1]
-        return None
+    def per_colouring(ds):
+        copy = [v for name, v in ds if "copybuffer" in name.lower()]
+        ours = [(name, v) for name, v in ds if any(k in name for k in COUNT_KERNELS)]
+        if len(ours) % len(seq):
+            raise SystemExit(f"{len(ours)} count dispatches are not a whole number of {len(seq)}-kernel colourings")
+        per = []
+        for c0 in range(0, len(ours), len(seq)):
+            total = 0.0
+            for (name, v), (kname, split) in zip(ours[c0:c0 + len(seq)], seq):
+                if kname not in name:
+                    raise SystemExit(f"dispatch {name} where {kname} was expected")
+                if split == dom:
+                    total += v
+            per.append(total)
+        return per, (sorted(copy[:3])[1] if len(copy) >= 3 else None)
 
-    fk, wk = copy_kib(fetch), copy_kib(write)
-    f_factor = copy_bytes / (fk * 1024.0) if fk else 1.0
-    w_factor = copy_bytes / (wk * 1024.0) if wk else 1.0
-    # dispatches of the split kernel in launch order; the dominant split index picks one per colouring
-    fsplit = [v for name, vs in fetch.items() if "k_split" in name for v in vs]
-    wsplit = [v for name, vs in write.items() if "k_split" in name for v in vs]
-    nspl = args.n_splits
-    idx = args.split_index
-    fsel = [fsplit[i] for i in range(idx, len(fsplit), nspl)]
-    wsel = [wsplit[i] for i in range(idx, len(wsplit), nspl)]
-    fetch_kib = sum(fsel) / len(fsel)
-    write_kib = sum(wsel) / len(wsel)
-    res = {"workload": args.workload, "kernel_hash": kernel_hash(args.workload), "split_index": idx,
-           "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
+    fper, fk = per_colouring(dispatches(rows(args.fetch_dir), "FETCH_SIZE"))
+    wper, wk = per_colouring(dispatches(rows(args.write_dir), "WRITE_SIZE"))
+    f_factor = args.copy_bytes / (fk * 1024.0) if fk else 1.0
+    w_factor = args.copy_bytes / (wk * 1024.0) if wk else 1.0
+    fetch_kib = sum(fper) / len(fper)
+    write_kib = sum(wper) / len(wper)
+    res = {"workload": args.workload, "kernel_hash": kernel_hash(args.workload), "split_index": dom,
+           "kernels": sorted({k for k, s_ in seq if s_ == dom}), "colourings": len(fper),
+           "fetch_kib_per_colouring": fetch_kib, "write_kib_per_colouring": write_kib,
            "copy_fetch_factor": f_factor, "copy_write_factor": w_factor,
            "traffic_bytes_per_launch": fetch_kib * 1024.0 * f_factor + write_kib * 1024.0 * w_factor,
            "command": args.command}
-    path = os.path.join(ROOT, "profiles", f"k_split_{args.workload}_pmc.json")
+    path = args.out or os.path.join(ROOT, "gpurun_out", f"pmc_{args.workload}.json")
     json.dump(res, open(path, "w"), indent=1)
     print(json.dumps(res))
 
@@ -706,22 +893,28 @@ def main():
                     help="requests of the capacity run and of each arrival rate (the same requests)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95],
                     help="Poisson arrival rates as fractions of the measured capacity")
-    ap.add_argument("--serve-mix", default="light", choices=sorted(SERVE_MIXES))
+    ap.add_argument("--serve-mix", default="bench", choices=sorted(SERVE_MIXES))
     ap.add_argument("--serve-cap", type=int, default=16,
                     help="colourings of one request per batch (0: as many as fit)")
     ap.add_argument("--serve-fifo-load", type=float, default=0.95,
                     help="also run this load without the cap, first come first served (0: skip)")
     ap.add_argument("--only-serving", action="store_true", help="run only the serving leg")
+    ap.add_argument("--only-budget", action="store_true",
+                    help="count one colouring of --workload within --budget-gb of device workspace")
+    ap.add_argument("--budget-gb", type=float, default=260.0)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--budget-frac", type=float, default=0.9,
+                    help="also count one colouring within this fraction of the plain workspace (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--summarize-pmc", action="store_true")
     ap.add_argument("--fetch-dir")
     ap.add_argument("--write-dir")
     ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
-    ap.add_argument("--split-index", type=int, default=0)
-    ap.add_argument("--n-splits", type=int, default=11)
+    ap.add_argument("--dispatch-map", default="",
+                    help="write (bench run) or read (--summarize-pmc) the count's kernel sequence per colouring")
+    ap.add_argument("--out", default="")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -742,6 +935,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.only_budget:
+        print(json.dumps({"beyond_hbm": beyond_hbm(args)}), flush=True)
+        return 0
     if args.only_serving:
         print(json.dumps({"serving": serving_leg(args)}), flush=True)
         return 0

@@ -180,6 +180,10 @@ typedef struct {
      * pass. Results are exact below 2^53 either way, and bit-identical when a passive row fits in
      * one pass of the gather (the same terms reach each sum in the same order). */
     int32_t proj_classes;
+    /* packed counts: doubles of one neighbour's row tile (the colourings of a tile side by side)
+     * that a wavefront reads per pass, 128, 256 or 512 (0 = auto: 256 when p >= 2, 512 when
+     * p = 1); more colourings per tile read each CSR entry fewer times but hold more registers */
+    int32_t packed_tile;
 } cc_tuning;
 
 /* flags for cc_graph_prepare */
@@ -204,7 +208,7 @@ typedef struct {
     int64_t n, nnz;
     int64_t max_degree;
     int64_t n_light, n_hubs, n_chunks;
-    int32_t hub_threshold, chunk, cols_per_lane, proj_classes;
+    int32_t hub_threshold, chunk, cols_per_lane, proj_classes, packed_tile;
 } cc_graph_info;
 
 cc_status cc_graph_info_get(const cc_graph* g, cc_graph_info* out);
@@ -265,6 +269,44 @@ cc_status cc_count(const cc_plan* plan, const cc_graph* g, const uint8_t* colour
 #define CC_NOALLOC_SCRATCH_BYTES (128u << 20)  /* 128 MiB per GPU */
 cc_status cc_count_noalloc(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
                            double* X_dev, double* vertex_dev, void* stream);
+
+/*
+ * Count within a device-memory budget (the paper's concern with the peak memory of intermediate
+ * count tables, Section 3.2, Eq. (peakm), and Section 4.4). The live tables of Eq. 1 peak where a
+ * large table waits between two uses while others are computed (for example the active table of
+ * the root split, written early and read last). cc_count_budget parks such tables in host memory:
+ * a parked table goes to the caller's host buffer after its last use before the idle stretch and
+ * comes back into the device arena just before its next reader; the arena is laid out again
+ * without it in between (tables placed largest first, each at the lowest columns free over its
+ * lifetime). Tables are chosen greedily until the arena fits the budget: the largest table idle at
+ * the split where the resident columns peak. The kernels and their
+ * order are those of cc_count, so the counts are bit-identical to cc_count's; only where the
+ * tables live changes (copies are queued on `stream` and ordered with the kernels). When no table
+ * is idle at the peak, the scratch of projected passive rows (cc_tuning.proj_classes) shrinks to
+ * fewer colour classes per pass, then to none (more passes: exact below 2^53 and 1e-12 above
+ * against cc_count, bit-identical when every passive row fits one gather pass).
+ *
+ * cc_count_budget_plan reports, for this plan, graph and budget (bytes of device workspace),
+ * the workspace and host bytes cc_count_budget needs, how many tables it parks, and the table
+ * arena with and without parking (in per-vertex doubles); CC_ENOSPC when even parking every
+ * table idle at the peak does not meet the budget. host_buf: host memory of host_bytes, page-
+ * locked for asynchronous copies (hipHostMalloc, or torch's pin_memory), owned by the caller and
+ * left untouched when no table is parked. Other arguments and errors as cc_count.
+ */
+typedef struct {
+    size_t workspace_bytes;    /* device workspace cc_count_budget needs (<= the budget when it fits) */
+    size_t host_bytes;         /* host bytes of the parked tables */
+    int32_t parked_tables;     /* tables parked over an idle stretch (between two uses) */
+    int32_t proj_classes;      /* most colour classes per pass of projected rows (0: none projected) */
+    int64_t arena_columns;     /* device table arena, per-vertex doubles */
+    int64_t unbounded_columns; /* the arena of cc_count */
+} cc_budget_info;
+
+cc_status cc_count_budget_plan(const cc_plan* plan, const cc_graph* g, size_t device_budget, cc_budget_info* out);
+
+cc_status cc_count_budget(const cc_plan* plan, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
+                          size_t device_budget, void* ws_dev, size_t ws_bytes, void* host_buf, size_t host_bytes,
+                          double* X_dev, double* vertex_dev, void* stream);
 
 /*
  * Inspection of one step of the dynamic program (Section 2.1, Eq. 1: the table C(., T_i, .) of a
@@ -359,6 +401,28 @@ cc_status cc_count_packed_multi_workspace_bytes(const cc_multi* multi, const cc_
  */
 cc_status cc_count_packed_multi(const cc_multi* multi, const cc_graph* g, const uint8_t* colours_dev, int32_t B,
                                 void* ws_dev, size_t ws_bytes, double* X_dev, void* stream);
+
+/* Device workspace of cc_count_packed_multi_persistent for this multi-template count, graph and B. */
+cc_status cc_count_packed_multi_persistent_workspace_bytes(const cc_multi* multi, const cc_graph* g, int32_t B,
+                                                           size_t* bytes);
+
+/*
+ * The same counts as cc_count_packed_multi (bit for bit: every item runs the same device code on
+ * the same tiles), in one persistent launch over (split, task or cut row, colouring tile) items:
+ * the outer loop of Algorithm 1 over B colourings and every template's splits of Eq. 1
+ * (Section 2.1), the neighbour lists cut into tasks as in Section 3.3, Algorithm 4. The splits are
+ * grouped by dependency level; each level's tasks, then its cut-row finishes, are dealt to the
+ * resident workgroups, with a device-wide barrier between phases (a cooperative launch, so every
+ * workgroup is resident and the barrier cannot wait on one that never runs). Tables are placed so
+ * that the splits of one level never share memory. Then the per-template root sums.
+ * Every split must run the packed kernels (rows of at most 64 entries per colouring: templates of
+ * up to 7 vertices, or wider templates whose splits stay narrow); CC_ERANGE otherwise. A barrier
+ * that does not open within about 10 s (which a resident grid cannot cause) makes every count NaN.
+ * The multi object holds the launch's host descriptors until the next call: concurrent calls with
+ * one multi object must be serialised by the caller.
+ */
+cc_status cc_count_packed_multi_persistent(const cc_multi* multi, const cc_graph* g, const uint8_t* colours_dev,
+                                           int32_t B, void* ws_dev, size_t ws_bytes, double* X_dev, void* stream);
 
 /* Synchronise `stream` and report any device error of the work queued on it (CC_EDEVICE). */
 cc_status cc_stream_check(void* stream);

@@ -60,11 +60,19 @@ class _TableDesc(ctypes.Structure):
                 ("offset", ctypes.c_int64)]
 
 
+class _BudgetInfo(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_size_t), ("host_bytes", ctypes.c_size_t),
+                ("parked_tables", ctypes.c_int32), ("proj_classes", ctypes.c_int32),
+                ("arena_columns", ctypes.c_int64),
+                ("unbounded_columns", ctypes.c_int64)]
+
+
 class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("n_light", ctypes.c_int64), ("n_hubs", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
                 ("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("cols_per_lane", ctypes.c_int32), ("proj_classes", ctypes.c_int32)]
+                ("cols_per_lane", ctypes.c_int32), ("proj_classes", ctypes.c_int32),
+                ("packed_tile", ctypes.c_int32)]
 
 
 class _Instance(ctypes.Structure):
@@ -81,7 +89,8 @@ def CC_BATCH_SHARE(d: int) -> int:
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("hub_threshold", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("cols_per_lane", ctypes.c_int32), ("proj_classes", ctypes.c_int32)]
+                ("cols_per_lane", ctypes.c_int32), ("proj_classes", ctypes.c_int32),
+                ("packed_tile", ctypes.c_int32)]
 
 
 EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split_get",
@@ -89,10 +98,12 @@ EXPORTS = ["cc_last_error", "cc_plan_create", "cc_plan_info_get", "cc_plan_split
            "cc_plan_constants_get", "cc_graph_workspace_bytes", "cc_graph_prepare",
            "cc_graph_info_get", "cc_graph_release", "cc_color", "cc_count_workspace_bytes", "cc_count",
            "cc_count_inspect", "cc_plan_table_get", "cc_count_projection", "cc_count_noalloc",
+           "cc_count_budget_plan", "cc_count_budget",
            "cc_count_packed_workspace_bytes", "cc_count_packed", "cc_stream_check", "cc_iterations",
            "cc_multi_create", "cc_multi_info_get", "cc_multi_step_get", "cc_multi_destroy",
            "cc_count_packed_multi_workspace_bytes",
-           "cc_count_packed_multi",
+           "cc_count_packed_multi", "cc_count_packed_multi_persistent_workspace_bytes",
+           "cc_count_packed_multi_persistent",
            "cc_estimate", "cc_estimate_median_of_means", "cc_profile_enable", "cc_profile_read",
            "cc_batch_create", "cc_batch_workspace_bytes", "cc_batch_run", "cc_batch_check", "cc_batch_destroy"]
 
@@ -128,6 +139,9 @@ def lib() -> ctypes.CDLL:
         "cc_plan_table_get": (ctypes.c_int, [P, P, I32, ctypes.POINTER(_TableDesc)]),
         "cc_count_projection": (ctypes.c_int, [P, P, P, I32]),
         "cc_count_noalloc": (ctypes.c_int, [P, P, P, I32, P, P, P]),
+        "cc_count_budget_plan": (ctypes.c_int, [P, P, ctypes.c_size_t, ctypes.POINTER(_BudgetInfo)]),
+        "cc_count_budget": (ctypes.c_int, [P, P, P, I32, ctypes.c_size_t, P, ctypes.c_size_t, P, ctypes.c_size_t,
+                                           P, P, P]),
         "cc_count_packed_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P, P]),
         "cc_stream_check": (ctypes.c_int, [P]),
@@ -137,6 +151,9 @@ def lib() -> ctypes.CDLL:
         "cc_multi_destroy": (None, [P]),
         "cc_count_packed_multi_workspace_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_size_t)]),
         "cc_count_packed_multi": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P]),
+        "cc_count_packed_multi_persistent_workspace_bytes": (ctypes.c_int, [P, P, I32,
+                                                                            ctypes.POINTER(ctypes.c_size_t)]),
+        "cc_count_packed_multi_persistent": (ctypes.c_int, [P, P, P, I32, P, ctypes.c_size_t, P, P]),
         "cc_iterations": (ctypes.c_int, [I32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(I64),
                                          ctypes.POINTER(I32)]),
         "cc_estimate": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double),
@@ -270,14 +287,14 @@ class Graph:
     """A CSR graph resident on the GPU (int64 row_ptr, int32 col) with its prepared work lists."""
 
     def __init__(self, row_ptr, col, hub_threshold: int = 0, chunk: int = 0, trust: bool = False,
-                 cols_per_lane: int = 0, proj_classes: int = 0, stream=None):
+                 cols_per_lane: int = 0, proj_classes: int = 0, packed_tile: int = 0, stream=None):
         import torch
         self.row_ptr = row_ptr
         self.col = col
         n = row_ptr.numel() - 1
         nnz = col.numel()
         self.n, self.nnz = n, nnz
-        tun = _Tuning(hub_threshold, chunk, cols_per_lane, proj_classes)
+        tun = _Tuning(hub_threshold, chunk, cols_per_lane, proj_classes, packed_tile)
         nb = ctypes.c_size_t()
         _check(lib().cc_graph_workspace_bytes(n, nnz, ctypes.byref(tun), ctypes.byref(nb)))
         self._ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=row_ptr.device)
@@ -385,6 +402,49 @@ def count_noalloc(plan: Plan, graph: Graph, colours, out, vertex_out=None, strea
                                   _dev_ptr(out, torch.float64, "out"), _dev_ptr(vertex_out, torch.float64, "vertex_out"),
                                   _stream(stream)))
     return out
+
+
+def count_budget_plan(plan: Plan, graph: Graph, budget: int) -> dict:
+    """cc_count_budget_plan: the device workspace, host bytes, parked tables and arena widths of a
+    count within `budget` bytes of device workspace (CCError CC_ENOSPC if it cannot fit)."""
+    info = _BudgetInfo()
+    rc = lib().cc_count_budget_plan(plan.handle, graph.handle, int(budget), ctypes.byref(info))
+    out = {f[0]: getattr(info, f[0]) for f in _BudgetInfo._fields_}
+    _check(rc)
+    return out
+
+
+def count_budget(plan: Plan, graph: Graph, colours, budget: int, per_vertex: bool = False,
+                 workspace: Workspace | None = None, host=None, out=None, vertex_out=None, stream=None):
+    """X[b] for each colouring row of `colours` within `budget` bytes of device workspace
+    (cc_count_budget): tables idle across the peak wait in `host` (a pinned uint8 CPU tensor that
+    must stay alive until the stream has passed the count; when None, one is allocated here and the
+    call waits for the stream before returning)."""
+    import torch
+    if colours.dim() == 1:
+        colours = colours.view(1, -1)
+    B = colours.shape[0]
+    if colours.shape[1] != graph.n:
+        raise ValueError("colours must be [B, n]")
+    info = count_budget_plan(plan, graph, budget)
+    dev = graph.row_ptr.device
+    ws = (workspace or Workspace()).get(info["workspace_bytes"], dev)
+    own_host = host is None
+    if own_host:
+        host = torch.empty(max(info["host_bytes"], 1), dtype=torch.uint8, pin_memory=True)
+    if host.is_cuda or host.numel() < info["host_bytes"]:
+        raise ValueError("host must be a CPU tensor of at least host_bytes bytes")
+    X = out if out is not None else torch.empty(B, dtype=torch.float64, device=dev)
+    V = None
+    if per_vertex:
+        V = vertex_out if vertex_out is not None else torch.empty((B, graph.n), dtype=torch.float64, device=dev)
+    _check(lib().cc_count_budget(plan.handle, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B, int(budget),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(host.data_ptr()),
+                                 host.numel(), _dev_ptr(X, torch.float64, "X"),
+                                 _dev_ptr(V, torch.float64, "vertex_out"), _stream(stream)))
+    if own_host:
+        (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+    return (X, V) if per_vertex else X
 
 
 def count_inspect(plan: Plan, graph: Graph, colours, last: int, workspace: Workspace | None = None,
@@ -499,13 +559,18 @@ class Multi:
             out.append((p.value, j.value))
         return out
 
-    def workspace_bytes(self, graph: "Graph", B: int) -> int:
+    def workspace_bytes(self, graph: "Graph", B: int, persistent: bool = False) -> int:
         nb = ctypes.c_size_t()
-        _check(lib().cc_count_packed_multi_workspace_bytes(self._h, graph.handle, B, ctypes.byref(nb)))
+        fn = (lib().cc_count_packed_multi_persistent_workspace_bytes if persistent
+              else lib().cc_count_packed_multi_workspace_bytes)
+        _check(fn(self._h, graph.handle, B, ctypes.byref(nb)))
         return nb.value
 
-    def count(self, graph: "Graph", colours, workspace: Workspace | None = None, out=None, stream=None):
-        """X[p, b] for every template p and colouring b of `colours` ([B, n] uint8 on the GPU)."""
+    def count(self, graph: "Graph", colours, workspace: Workspace | None = None, out=None, stream=None,
+              persistent: bool = False):
+        """X[p, b] for every template p and colouring b of `colours` ([B, n] uint8 on the GPU):
+        one launch per split (cc_count_packed_multi) or one persistent launch for all of them
+        (cc_count_packed_multi_persistent, persistent=True)."""
         import torch
         if colours.dim() == 1:
             colours = colours.view(1, -1)
@@ -513,11 +578,11 @@ class Multi:
         if colours.shape[1] != graph.n:
             raise ValueError("colours must be [B, n]")
         dev = graph.row_ptr.device
-        ws = (workspace or Workspace()).get(self.workspace_bytes(graph, B), dev)
+        ws = (workspace or Workspace()).get(self.workspace_bytes(graph, B, persistent), dev)
         X = out if out is not None else torch.empty((len(self.plans), B), dtype=torch.float64, device=dev)
-        _check(lib().cc_count_packed_multi(self._h, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B,
-                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                                           _dev_ptr(X, torch.float64, "X"), _stream(stream)))
+        fn = lib().cc_count_packed_multi_persistent if persistent else lib().cc_count_packed_multi
+        _check(fn(self._h, graph.handle, _dev_ptr(colours, torch.uint8, "colours"), B,
+                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _dev_ptr(X, torch.float64, "X"), _stream(stream)))
         return X
 
     def __del__(self):

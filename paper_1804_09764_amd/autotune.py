@@ -1,4 +1,5 @@
-"""Degree-split autotuner: picks a graph's work-split parameters for a template by measurement.
+"""Autotuners: a graph's work-split parameters for a template (tune) and for a batched
+multi-template count (tune_multi), chosen by measurement.
 
 The paper's load balancing (Section 3.3, Algorithm 4) partitions the neighbour lists of high-degree
 vertices into tasks of a fixed size and reports that the task size matters (its Fig. 11 sweeps it).
@@ -11,6 +12,10 @@ the chunking changes only the summation order of the cut rows).
 Records are keyed by what decides the choice: the device, k, the passive row widths of the plan's
 splits, and the graph's size and degree profile (log2 of the mean and of the largest degree). A
 record cache can be kept in a JSON file and reused by later runs.
+
+tune_multi does the same for the batched path (a multi-template packed count of B colourings):
+the degree split, then the tile row of the packed kernels (cc_tuning.packed_tile: how many
+colourings of a neighbour's row a wavefront reads per pass).
 """
 from __future__ import annotations
 
@@ -118,6 +123,94 @@ def tune(plan: Plan, row_ptr, col, seed: int = 1, repeats: int = 2, cache_path: 
     c0 = default_chunk(nnz)
     rec = TuneRecord(hub_threshold=tau, chunk=c, ms=timings[best], default_ms=timings[f"{2 * c0},{c0}"],
                      timings=timings)
+    if cache_path:
+        cache[key] = asdict(rec)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return rec
+
+
+@dataclass
+class MultiTuneRecord:
+    hub_threshold: int
+    chunk: int
+    packed_tile: int                            # 0 = the library's automatic tile
+    ms: float                                   # milliseconds of one multi-template count, the choice
+    default_ms: float                           # the library default's, same measurement
+    timings: dict = field(default_factory=dict)  # "tau,c,tile" -> ms
+
+
+def multi_record_key(plans, n: int, nnz: int, max_degree: int, B: int, device: str) -> str:
+    widths = sorted({math.comb(p.k - 1, q - 1) for p in plans for (_, _, q) in p.splits})
+    mean = nnz / max(n, 1)
+    return json.dumps({"device": device, "k": plans[0].k, "templates": len(plans), "B": B,
+                       "passive_widths": widths, "n": n, "nnz": nnz,
+                       "log2_mean_degree": int(math.floor(math.log2(mean))) if mean >= 1 else -1,
+                       "log2_max_degree": int(math.floor(math.log2(max_degree))) if max_degree >= 1 else -1},
+                      sort_keys=True)
+
+
+TILES = (0, 128, 512)
+
+
+def tune_multi(plans, row_ptr, col, B: int, seed: int = 1, repeats: int = 2, cache_path: str | None = None,
+               trust: bool = False) -> MultiTuneRecord:
+    """The batched path's parameters by measurement (the task-size sweep of Section 3.3 / Fig. 11
+    applied to a multi-template packed count of B colourings): first the degree split (tau, c) over
+    candidates() with the automatic tile, then the tile row (packed_tile in TILES) at the best
+    (tau, c). Every candidate counts the same colourings and must agree with the first (exact below
+    2^53, 1e-12 relative above); the fastest is returned (and cached in `cache_path`)."""
+    import torch
+    from . import Multi
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    degrees = (row_ptr[1:] - row_ptr[:-1]) if n > 0 else row_ptr[:0]
+    max_degree = int(degrees.max().item()) if n > 0 else 0
+    device = torch.cuda.get_device_name(row_ptr.device)
+    key = multi_record_key(plans, n, nnz, max_degree, B, device)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            return MultiTuneRecord(**cache[key])
+    multi = Multi(plans)
+    ws = Workspace()
+    timings: dict[str, float] = {}
+    state = {"ref": None, "validated": trust, "C": None}
+
+    def run(tau, c, tile):
+        G = Graph(row_ptr, col, hub_threshold=tau, chunk=c, packed_tile=tile, trust=state["validated"])
+        state["validated"] = True
+        if state["C"] is None:
+            state["C"] = colour(G, plans[0].k, seed=seed, first_iter=0, B=B)
+        X = multi.count(G, state["C"], workspace=ws)
+        torch.cuda.synchronize()
+        x = X.cpu().numpy().ravel()
+        if state["ref"] is None:
+            state["ref"] = x
+        elif not all(_agree(float(a), float(b)) for a, b in zip(x, state["ref"])):
+            raise RuntimeError(f"tau={tau} c={c} tile={tile}: counts differ from the first candidate's")
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            multi.count(G, state["C"], workspace=ws, out=X)
+        torch.cuda.synchronize()
+        timings[f"{tau},{c},{tile}"] = (time.perf_counter() - t0) * 1e3 / repeats
+        del G
+
+    for tau, c in candidates(nnz, max_degree):
+        run(tau, c, 0)
+    best = min(timings, key=timings.get)
+    tau, c, _ = (int(v) for v in best.split(","))
+    for tile in TILES[1:]:
+        run(tau, c, tile)
+    best = min(timings, key=timings.get)
+    tau, c, tile = (int(v) for v in best.split(","))
+    c0 = default_chunk(nnz)
+    rec = MultiTuneRecord(hub_threshold=tau, chunk=c, packed_tile=tile, ms=timings[best],
+                          default_ms=timings[f"{2 * c0},{c0},0"], timings=timings)
     if cache_path:
         cache[key] = asdict(rec)
         tmp = cache_path + ".tmp"

@@ -102,16 +102,21 @@ struct CountLayout {
     std::vector<int> proj;  // classes per projected pass of each split (0: none)
 };
 
-CountLayout count_layout(const cc_plan* P, const cc_graph* G) {
+// arena_cols: the table arena's width in columns of n_pad doubles (-1: the plan's own);
+// proj_cap: at most this many colour classes per projected pass (0: no projection; -1: no cap)
+CountLayout count_layout(const cc_plan* P, const cc_graph* G, int64_t arena_cols = -1, int proj_cap = -1) {
     CountLayout L;
     L.n_pad = pad32(G->n);
     L.arena_off = 0;
-    L.partial_off = align256((size_t)P->arena_cols * (size_t)L.n_pad * sizeof(double));
+    if (arena_cols < 0) arena_cols = P->arena_cols;
+    L.partial_off = align256((size_t)arena_cols * (size_t)L.n_pad * sizeof(double));
     L.root_off = align256(L.partial_off + (size_t)G->n_chunks * (size_t)P->max_stride_N * sizeof(double));
     L.red_off = align256(L.root_off + (size_t)std::max<int64_t>(G->n, 1) * sizeof(double));
     L.ecol_off = align256(L.red_off + 1024 * sizeof(double));
     L.proj_off = align256(L.ecol_off + (size_t)std::max<int64_t>(G->nnz, 1));
     L.proj = projection_plan(P, G, L.n_pad);
+    if (proj_cap >= 0)
+        for (int& c : L.proj) c = std::min(c, proj_cap);
     size_t proj_bytes = 0;
     for (size_t i = 0; i < P->splits.size(); ++i)
         proj_bytes = std::max(proj_bytes, (size_t)L.proj[i] * (size_t)L.n_pad * (size_t)P->splits[i].Wn_pad * sizeof(double));
@@ -172,6 +177,7 @@ cc::StepParams base_params(const cc_plan* P, const cc_graph* G, const cc::Split&
     h.cols_per_lane = G->cols_per_lane;
     h.cls_mask = cc::kAllClasses;
     h.class_stride = 0;
+    h.tile_doubles = G->packed_tile;
     h.k = P->k;
     h.s = sp.s;
     h.a = sp.a;
@@ -467,6 +473,9 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     resolve_tuning(nnz, tuning, &thr, &chunk, &cols);
     if (tuning && (tuning->proj_classes < -1 || tuning->proj_classes > CC_MAX_K))
         return fail(CC_EINVAL, "proj_classes must be -1, 0 or 1..16");
+    if (tuning && tuning->packed_tile != 0 && tuning->packed_tile != 128 && tuning->packed_tile != 256 &&
+        tuning->packed_tile != 512)
+        return fail(CC_EINVAL, "packed_tile must be 0, 128, 256 or 512");
     if (cols != 0 && cols != 1 && cols != 2 && cols != 4 && cols != 8 && cols != 16)
         return fail(CC_EINVAL, "cols_per_lane must be 0, 1, 2, 4, 8 or 16");
     GraphLayout L = graph_layout(n, nnz, thr, chunk);
@@ -568,6 +577,7 @@ cc_status cc_graph_prepare(int64_t n, int64_t nnz, const int64_t* row_ptr_dev, c
     G->chunk = chunk;
     G->cols_per_lane = cols;
     G->proj_classes = tuning ? tuning->proj_classes : 0;
+    G->packed_tile = tuning ? tuning->packed_tile : 0;
     e = hipGetDevice(&G->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&G->n_cu, hipDeviceAttributeMultiprocessorCount, G->device);
     if (e == hipSuccess && !light.empty())
@@ -599,6 +609,7 @@ cc_status cc_graph_info_get(const cc_graph* G, cc_graph_info* o) {
     o->chunk = G->chunk;
     o->cols_per_lane = G->cols_per_lane;
     o->proj_classes = G->proj_classes;
+    o->packed_tile = G->packed_tile;
     return CC_OK;
 }
 
@@ -632,8 +643,23 @@ namespace {
 
 // Splits [0, last] of plan P for one colouring on `st`: the per-entry neighbour colours, then
 // every split's gather + combine and cut-row finish, timed per split while profiling.
+// Where each table of a count lives when some tables are parked in host memory over an idle
+// stretch (cc_count_budget): a parked table t holds columns off_a[t] from its production to split
+// g0[t] (its last use before the stretch, or its production), is copied to the caller's host
+// buffer at host_off[t] after split g0[t], and comes back into columns off_b[t] just before split
+// g1[t] (its next use), where it stays until its last use. Unparked tables hold off_a for their
+// whole life (off_b = off_a).
+struct Placement {
+    std::vector<int64_t> off_a, off_b;
+    std::vector<int> parked, g0, g1;
+    std::vector<size_t> host_off;
+    uint8_t* host = nullptr;
+    // columns of table t for split j
+    int64_t off(size_t t, int j) const { return (parked[t] && j >= g1[t]) ? off_b[t] : off_a[t]; }
+};
+
 hipError_t run_splits(const cc_plan* P, const cc_graph* G, const uint8_t* colour, const CountLayout& L, uint8_t* ws,
-                      double* root_out, int64_t last, hipStream_t st) {
+                      double* root_out, int64_t last, hipStream_t st, const Placement* PL = nullptr) {
     double* arena = (double*)(ws + L.arena_off);
     double* partial = (double*)(ws + L.partial_off);
     uint8_t* ecol = ws + L.ecol_off;
@@ -668,10 +694,22 @@ hipError_t run_splits(const cc_plan* P, const cc_graph* G, const uint8_t* colour
         if (err == hipSuccess) err = cc::launch_hub_finish(h, G->n_cu, st);
         return err;
     };
+    // bytes of one table's rows (vertex-major, n rows of its stride)
+    auto table_bytes = [&](int t) { return (size_t)G->n * (size_t)P->tables[(size_t)t].stride * sizeof(double); };
     for (int64_t i = 0; e == hipSuccess && i <= last; ++i) {
         const cc::Split& sp = P->splits[(size_t)i];
         cc::StepParams h = step_params(P, G, sp, colour, arena, L.n_pad, partial, root_out);
         h.ecol = ecol;
+        if (PL) {
+            // parked tables read again by this split come back from host memory
+            for (size_t t = 0; e == hipSuccess && t < P->tables.size(); ++t)
+                if (PL->parked[t] && PL->g1[t] == (int)i)
+                    e = hipMemcpyAsync(arena + PL->off_b[t] * L.n_pad, PL->host + PL->host_off[t], table_bytes((int)t),
+                                       hipMemcpyHostToDevice, st);
+            if (sp.act >= 0) h.A = arena + PL->off((size_t)sp.act, (int)i) * L.n_pad;
+            if (sp.pas >= 0) h.P = arena + PL->off((size_t)sp.pas, (int)i) * L.n_pad;
+            if (sp.out >= 0) h.O = arena + PL->off((size_t)sp.out, (int)i) * L.n_pad;
+        }
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
         if (P->profiling) {
             for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
@@ -688,8 +726,150 @@ hipError_t run_splits(const cc_plan* P, const cc_graph* G, const uint8_t* colour
             pe.push_back(ev[2]);
             P->prof_launches[(size_t)i] += 1;
         }
+        // a table parked after this split goes to host memory now; its device columns are reused
+        // by later splits only after the copy (the stream orders them)
+        for (size_t t = 0; e == hipSuccess && PL && t < P->tables.size(); ++t)
+            if (PL->parked[t] && PL->g0[t] == (int)i)
+                e = hipMemcpyAsync(PL->host + PL->host_off[t], arena + PL->off_a[t] * L.n_pad, table_bytes((int)t),
+                                   hipMemcpyDeviceToHost, st);
     }
     return e;
+}
+
+// Tables parked in host memory so that a count fits a device budget. Each table lives over an
+// interval of splits (from the split that writes it to its last reader); parking it over an idle
+// stretch (between two consecutive uses, the write counting as one) splits that interval in two.
+// Columns are assigned to the intervals largest first, each at the lowest offset free over its
+// whole interval. While that arena exceeds the budget, the largest table idle at the split where
+// the resident columns peak is parked over that stretch (one stretch per table).
+struct BudgetLayout {
+    CountLayout L;
+    Placement PL;
+    int64_t arena_cols = 0, unbounded_cols = 0;
+    int parked = 0;
+    size_t host_bytes = 0;
+    bool fits = false;
+};
+
+BudgetLayout budget_layout(const cc_plan* P, const cc_graph* G, size_t budget) {
+    BudgetLayout B;
+    const size_t nt = P->tables.size(), ns = P->splits.size();
+    // the splits that write and read each table, in order
+    std::vector<std::vector<int>> events(nt);
+    for (size_t j = 0; j < ns; ++j) {
+        const cc::Split& sp = P->splits[j];
+        for (int t : {sp.out, sp.act, sp.pas})
+            if (t >= 0 && (events[(size_t)t].empty() || events[(size_t)t].back() != (int)j))
+                events[(size_t)t].push_back((int)j);
+    }
+    Placement& PL = B.PL;
+    PL.parked.assign(nt, 0);
+    PL.g0.assign(nt, -1);
+    PL.g1.assign(nt, -1);
+    auto stride = [&](size_t t) { return (int64_t)P->tables[t].stride; };
+    struct Iv {
+        int64_t len;
+        int s, e;
+        size_t t;
+        bool second;
+    };
+    // offsets for the current parking choice; returns the arena width
+    auto place = [&]() -> int64_t {
+        std::vector<Iv> iv;
+        for (size_t t = 0; t < nt; ++t) {
+            if (events[t].empty()) continue;
+            if (PL.parked[t]) {
+                iv.push_back({stride(t), events[t].front(), PL.g0[t], t, false});
+                iv.push_back({stride(t), PL.g1[t], events[t].back(), t, true});
+            } else {
+                iv.push_back({stride(t), events[t].front(), events[t].back(), t, false});
+            }
+        }
+        std::stable_sort(iv.begin(), iv.end(), [](const Iv& a, const Iv& b) {
+            return a.len != b.len ? a.len > b.len : a.s < b.s;
+        });
+        std::vector<std::pair<const Iv*, int64_t>> placed;
+        int64_t width = 0;
+        PL.off_a.assign(nt, 0);
+        PL.off_b.assign(nt, 0);
+        for (const Iv& x : iv) {
+            std::vector<std::pair<int64_t, int64_t>> busy;  // columns taken over x's splits
+            for (auto& pr : placed)
+                if (std::max(pr.first->s, x.s) <= std::min(pr.first->e, x.e)) busy.push_back({pr.second, pr.first->len});
+            std::sort(busy.begin(), busy.end());
+            int64_t off = 0;
+            for (auto& b : busy) {
+                if (b.first - off >= x.len) break;
+                off = std::max(off, b.first + b.second);
+            }
+            placed.push_back({&x, off});
+            width = std::max(width, off + x.len);
+            if (x.second) PL.off_b[x.t] = off;
+            else PL.off_a[x.t] = off;
+        }
+        for (size_t t = 0; t < nt; ++t)
+            if (!PL.parked[t]) PL.off_b[t] = PL.off_a[t];
+        return width;
+    };
+    B.unbounded_cols = P->arena_cols;
+    int proj_cap = -1;  // the projected rows' scratch shrinks once nothing more can be parked
+    for (;;) {
+        B.arena_cols = place();
+        B.L = count_layout(P, G, B.arena_cols, proj_cap);
+        if (B.L.total <= budget) {
+            B.fits = true;
+            break;
+        }
+        // the split where the most columns are resident
+        int64_t best_live = -1;
+        int jstar = 0;
+        for (size_t j = 0; j < ns; ++j) {
+            int64_t live = 0;
+            for (size_t t = 0; t < nt; ++t) {
+                if (events[t].empty()) continue;
+                const int J = (int)j;
+                const bool res = PL.parked[t] ? ((events[t].front() <= J && J <= PL.g0[t]) ||
+                                                 (PL.g1[t] <= J && J <= events[t].back()))
+                                              : (events[t].front() <= J && J <= events[t].back());
+                if (res) live += stride(t);
+            }
+            if (live > best_live) {
+                best_live = live;
+                jstar = (int)j;
+            }
+        }
+        // the largest unparked table resident but idle there: two consecutive events around jstar
+        int pick = -1, pg0 = -1, pg1 = -1;
+        for (size_t t = 0; t < nt; ++t) {
+            if (PL.parked[t]) continue;
+            const std::vector<int>& ev = events[t];
+            for (size_t q = 0; q + 1 < ev.size(); ++q)
+                if (ev[q] < jstar && jstar < ev[q + 1] && (pick < 0 || stride(t) > stride((size_t)pick))) {
+                    pick = (int)t;
+                    pg0 = ev[q];
+                    pg1 = ev[q + 1];
+                }
+        }
+        if (pick < 0) {
+            // nothing idle at the peak: fewer colour classes per projected pass, then none
+            int most = 0;
+            for (int c : B.L.proj) most = std::max(most, c);
+            if (most == 0) break;  // the budget cannot be met
+            proj_cap = most / 2;
+            continue;
+        }
+        PL.parked[(size_t)pick] = 1;
+        PL.g0[(size_t)pick] = pg0;
+        PL.g1[(size_t)pick] = pg1;
+        ++B.parked;
+    }
+    PL.host_off.assign(nt, 0);
+    for (size_t t = 0; t < nt; ++t)
+        if (PL.parked[t]) {
+            PL.host_off[t] = B.host_bytes;
+            B.host_bytes = align256(B.host_bytes + (size_t)G->n * (size_t)stride(t) * sizeof(double));
+        }
+    return B;
 }
 
 }  // namespace
@@ -724,6 +904,55 @@ cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_d
         }
         if (e == hipSuccess) e = cc::launch_reduce(root_out, n, red, X_dev + b, st);
         if (e != hipSuccess) return hip_fail(e, "count launch");
+    }
+    return CC_OK;
+}
+
+cc_status cc_count_budget_plan(const cc_plan* P, const cc_graph* G, size_t device_budget, cc_budget_info* o) {
+    if (!P || !G || !o) return fail(CC_EINVAL, "NULL argument");
+    const BudgetLayout Bl = budget_layout(P, G, device_budget);
+    o->workspace_bytes = Bl.L.total;
+    o->host_bytes = Bl.host_bytes;
+    o->parked_tables = Bl.parked;
+    o->proj_classes = 0;
+    for (int c : Bl.L.proj) o->proj_classes = std::max(o->proj_classes, c);
+    o->arena_columns = Bl.arena_cols;
+    o->unbounded_columns = Bl.unbounded_cols;
+    if (!Bl.fits) return fail(CC_ENOSPC, "the count does not fit this device budget even with tables parked in host memory");
+    return CC_OK;
+}
+
+cc_status cc_count_budget(const cc_plan* P, const cc_graph* G, const uint8_t* colours_dev, int32_t B,
+                          size_t device_budget, void* ws_dev, size_t ws_bytes, void* host_buf, size_t host_bytes,
+                          double* X_dev, double* vertex_dev, void* stream) {
+    if (!P || !G) return fail(CC_EINVAL, "NULL plan or graph");
+    if (B < 0) return fail(CC_EINVAL, "B must be >= 0");
+    if (B == 0) return CC_OK;
+    if (!X_dev || !ws_dev || (G->n > 0 && !colours_dev)) return fail(CC_EINVAL, "NULL buffer");
+    if (!P->splits.empty() && !P->dev) return fail(CC_EINVAL, "plan not bound to device memory");
+    BudgetLayout Bl = budget_layout(P, G, device_budget);
+    if (!Bl.fits) return fail(CC_ENOSPC, "the count does not fit this device budget even with tables parked in host memory");
+    if (ws_bytes < Bl.L.total) return fail(CC_ENOSPC, "count workspace too small");
+    if (Bl.host_bytes > 0 && (!host_buf || host_bytes < Bl.host_bytes))
+        return fail(CC_ENOSPC, "host buffer for the parked tables too small");
+    Bl.PL.host = (uint8_t*)host_buf;
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)ws_dev;
+    double* red = (double*)(ws + Bl.L.red_off);
+    const int64_t n = G->n;
+    hipError_t e = hipSuccess;
+    for (int32_t b = 0; b < B; ++b) {
+        double* root_out = vertex_dev ? vertex_dev + (int64_t)b * n : (double*)(ws + Bl.L.root_off);
+        if (n == 0) {
+            e = cc::launch_fill_f64(X_dev + b, 1, 0.0, st);
+            if (e != hipSuccess) return hip_fail(e, "fill");
+            continue;
+        }
+        const uint8_t* colour = colours_dev + (int64_t)b * n;
+        if (P->splits.empty()) e = cc::launch_fill_f64(root_out, n, 1.0, st);
+        else e = run_splits(P, G, colour, Bl.L, ws, root_out, (int64_t)P->splits.size() - 1, st, &Bl.PL);
+        if (e == hipSuccess) e = cc::launch_reduce(root_out, n, red, X_dev + b, st);
+        if (e != hipSuccess) return hip_fail(e, "budgeted count launch");
     }
     return CC_OK;
 }

@@ -156,6 +156,8 @@ struct StepParams {
     // b * W); colour points to the colours as [v][b]. B == 0 selects the one-colouring layout.
     int B;
     int bt;             // colourings per tile of a row (<= 64)
+    int tile_doubles;   // doubles of a tile row per neighbour (0: 256 when p >= 2, 512 when p = 1)
+    int force_J;        // tile elements per lane per pass (0: the smallest that covers a tile row)
     int Cf;             // C(k, p): neighbour-sum entries per colouring, over all k colours
     int tab_u16;        // entries of the block-shared maps at the start of LDS: FM (k * Wp) then E (k * Nw)
     int tab_doubles;    // their size in doubles (rounded up)
@@ -198,6 +200,28 @@ struct SegDesc {
 struct SegRange {
     int32_t first;
     int32_t count;
+};
+
+// One persistent launch of a multi-template packed count: the splits that run, grouped by
+// dependency level (a split's inputs come from earlier levels only). Each level has a task phase
+// (chunks of cut rows and light rows of every split of the level) and a cut-row finish phase;
+// a device-wide barrier separates consecutive phases. Work is dealt in item blocks: up to one
+// workgroup's worth of consecutive items of one split.
+struct PSeg {
+    StepParams S;        // packed arguments of the split (tile, maps, tables, scratch)
+    int32_t p1;          // 1 when the passive part is a single vertex (colour counts)
+    int32_t pad;
+};
+
+struct PItemBlock {
+    int32_t seg;         // index into the PSeg array
+    int32_t count;       // items in the block (<= waves per workgroup)
+    int64_t first;       // first item: a task (phase 0) or a cut row (phase 1) of the split
+};
+
+struct PPhase {
+    int64_t first_block; // item blocks [first_block, first_block + n_blocks) of the phase
+    int64_t n_blocks;
 };
 
 // per-instance root reduction of a batch
@@ -259,6 +283,18 @@ hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_
 hipError_t launch_transpose_colours(const uint8_t* in, int64_t n, int B, uint8_t* out, hipStream_t st);
 int packed_reduce_blocks(int64_t n);
 hipError_t launch_reduce_packed(const double* x, int64_t n, int B, double* partial, double* out, hipStream_t st);
+// the persistent multi-template launch: phases[0 .. n_phases) in order over the item blocks, all of
+// whose splits run the packed kernels; bar = 3 zeroed unsigned (barrier count, generation, error
+// flag), lds = dynamic LDS bytes for `waves` wavefronts per workgroup (the widest split's maps and
+// slices). Returns hipErrorCooperativeLaunchTooLarge when the grid cannot be co-resident.
+// Every split with p >= 2 takes JP tile elements per lane per pass and every split with p = 1 takes
+// kPersistentJ1 (StepParams.force_J), so that one kernel holds two variants only.
+constexpr int kPersistentJ1 = 8;
+hipError_t launch_packed_persistent(const PSeg* segs, const PItemBlock* blocks, const PPhase* phases_host,
+                                    const PPhase* phases_dev, int n_phases, int waves, int JP, size_t tab_doubles,
+                                    size_t lds_wave, unsigned* bar, int n_cu, hipStream_t st);
+// X[0 .. n) = NaN when *flag != 0 (queued after the root sums of a persistent launch)
+hipError_t launch_poison_if(const unsigned* flag, double* X, int64_t n, hipStream_t st);
 }  // namespace cc
 
 struct cc_graph {
@@ -273,6 +309,7 @@ struct cc_graph {
     int32_t hub_threshold = 0, chunk = 0;
     int32_t cols_per_lane = 0;
     int32_t proj_classes = 0;  // cc_tuning.proj_classes
+    int32_t packed_tile = 0;   // cc_tuning.packed_tile
     int device = 0;
     int n_cu = 0;
 };
@@ -290,6 +327,11 @@ struct cc_multi {
     std::vector<Step> steps;
     std::vector<int> table_W;  // per global table: entries per colouring
     int64_t n_splits = 0;      // splits of all plans together (before sharing)
+    // host copies of the persistent launch's descriptors (kept alive while the asynchronous
+    // uploads of the last call are in flight)
+    mutable std::vector<cc::PSeg> pseg_host;
+    mutable std::vector<cc::PItemBlock> pblock_host;
+    mutable std::vector<cc::PPhase> pphase_host;
 };
 
 struct cc_batch {

@@ -95,8 +95,9 @@ void packed_tile(StepParams* S) {
     const int per = S->Cf + (S->a >= 2 ? S->Wa : 0);
     const int width = S->p >= 2 ? S->Wp : S->k;
     int cap = S->B < kWave ? S->B : kWave;
-    // tile elements per lane: up to 4 (p >= 2: a tile row of about 2 KB) or 8 (p = 1: counts in registers)
-    const int elems = S->p >= 2 ? 256 : 512;
+    // tile elements per lane: up to 4 (p >= 2: a tile row of about 2 KB) or 8 (p = 1: counts in
+    // registers), unless the graph's tuning sets the tile row
+    const int elems = S->tile_doubles > 0 ? S->tile_doubles : (S->p >= 2 ? 256 : 512);
     const int by_width = elems / width > 1 ? elems / width : 1;
     const int by_lds = 1024 / per > 1 ? 1024 / per : 1;      // about 8 KB of LDS per wavefront
     if (cap > by_width) cap = by_width;
@@ -109,6 +110,7 @@ void packed_tile(StepParams* S) {
     S->bt = bt;
     int J = 1;
     while (J < 8 && kWave * J < bt * width) J <<= 1;
+    if (S->force_J > 0) J = S->force_J;
     S->pJ = J;
     // every offset is even (16-byte aligned) so that the colour stage takes 16-byte LDS stores
     auto even = [](int x) { return (x + 1) & ~1; };
@@ -176,6 +178,125 @@ hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_
         err = hipGetLastError();
     }
     return err;
+}
+
+// ---------------------------------------------------------------------------------------------
+// multi-template packed count in one persistent launch
+// ---------------------------------------------------------------------------------------------
+
+// Device-wide barrier of a cooperative launch (every workgroup is resident). bar[0] counts the
+// workgroups that arrived, bar[1] is the generation: the last to arrive resets the count and opens
+// the next generation. Stores before the barrier are released at device scope and loads after it
+// acquire at device scope, so tables written by one XCD are seen by the others. The wait is
+// bounded by the 100 MHz real-time counter: after about 10 s a workgroup stops waiting and sets
+// bar[2], so a barrier that never opens ends the kernel (with the error flag raised) instead of
+// hanging it.
+constexpr uint64_t kBarrierTicks = 1000000000ull;
+
+__device__ void grid_barrier(unsigned* bar, unsigned nblocks) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(bar + 1, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(8);
+                if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTicks) {
+                    __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// The phases in order (even: the tasks of a dependency level, odd: its cut-row finishes); a
+// workgroup takes item blocks round-robin, stages the block's split maps in LDS when the split
+// changes, and each of its wavefronts runs one item of the block.
+template <int JP>
+__global__ __launch_bounds__(256, 3) void k_pmulti(const PSeg* __restrict__ segs, const PItemBlock* __restrict__ blocks,
+                                                const PPhase* __restrict__ phases, int n_phases, int tab_doubles,
+                                                int lds_wave, unsigned* bar) {
+    extern __shared__ double lds[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
+    double* N = lds + tab_doubles + (int64_t)wib * lds_wave;
+    int staged = -1;
+    PMaps M{};
+    // the current split's arguments, staged in LDS with its maps (read from HBM they measured
+    // 25 % slower: fields are read inside the neighbour loops)
+    __shared__ StepParams Ssh;
+    for (int ph = 0; ph < n_phases; ++ph) {
+        const PPhase P = phases[ph];
+        const bool finish = (ph & 1) != 0;
+        for (int64_t b = blockIdx.x; b < P.n_blocks; b += gridDim.x) {
+            const PItemBlock ib = blocks[P.first_block + b];
+            const int seg = __builtin_amdgcn_readfirstlane(ib.seg);
+            if (seg != staged) {
+                __syncthreads();  // the workgroup is done with the previous maps
+                M = stage_maps(segs[seg].S, lds);
+                if (threadIdx.x == 0) Ssh = segs[seg].S;
+                __syncthreads();
+                staged = seg;
+            }
+            const StepParams& S = Ssh;
+            if (wib < ib.count) {
+                double* Ash = N + S.a_off;
+                if (finish) do_phub(S, ib.first + wib, N, Ash, M, lane);
+                else if (segs[seg].p1) do_ptask<kPersistentJ1, true>(S, ib.first + wib, N, Ash, M, lane);
+                else do_ptask<JP, false>(S, ib.first + wib, N, Ash, M, lane);
+            }
+        }
+        if (ph + 1 < n_phases) grid_barrier(bar, gridDim.x);
+    }
+}
+
+hipError_t launch_packed_persistent(const PSeg* segs, const PItemBlock* blocks, const PPhase* phases_host,
+                                    const PPhase* phases_dev, int n_phases, int waves, int JP, size_t tab_doubles,
+                                    size_t lds_wave, unsigned* bar, int n_cu, hipStream_t st) {
+    if (n_phases <= 0) return hipSuccess;
+    const size_t lds = (tab_doubles + lds_wave * (size_t)waves) * sizeof(double);
+    if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
+    const void* fn = JP == 1 ? (const void*)k_pmulti<1>
+                   : JP == 2 ? (const void*)k_pmulti<2>
+                   : JP == 4 ? (const void*)k_pmulti<4>
+                             : (const void*)k_pmulti<8>;
+    const int threads = waves * kWave;
+    int per_cu = 0;
+    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    if (err != hipSuccess) return err;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int64_t most = 1;
+    for (int i = 0; i < n_phases; ++i) most = phases_host[i].n_blocks > most ? phases_host[i].n_blocks : most;
+    int64_t grid = (int64_t)per_cu * n_cu;
+    if (grid > most) grid = most;
+    int nph = n_phases;
+    int tabd = (int)tab_doubles;
+    int lw = (int)lds_wave;
+    void* args[] = {(void*)&segs, (void*)&blocks, (void*)&phases_dev, &nph, &tabd, &lw, (void*)&bar};
+    err = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(threads), args, (unsigned)lds, st);
+    if (err != hipSuccess) return err;
+    return hipGetLastError();
+}
+
+// X[i] = NaN for i < n when flag[0] != 0 (a persistent launch whose barrier timed out)
+__global__ void k_poison_if(const unsigned* flag, double* X, int64_t n) {
+    if (*flag == 0u) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        X[i] = __builtin_nan("");
+}
+
+hipError_t launch_poison_if(const unsigned* flag, double* X, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_poison_if, dim3(1), dim3(256), 0, st, flag, X, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_transpose_colours(const uint8_t* in, int64_t n, int B, uint8_t* out, hipStream_t st) {
