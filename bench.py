@@ -42,7 +42,7 @@ WORKLOADS = {
     "rmat23-ef256-u12": dict(scale=23, ef=256, gseed=3, k=12, tseed=12, B=4, trust=True),
     "rmat20-ef16-u15": dict(scale=20, ef=16, gseed=1, k=15, tseed=15, B=1, trust=False),
     # a 15-vertex tree whose live tables exceed HBM (counted with --only-budget)
-    "rmat22-ef16-u15": dict(scale=22, ef=16, gseed=1, k=15, tseed=15, B=1, trust=True),
+    "rmat22-ef16-u15": dict(scale=22, ef=16, gseed=1, k=15, tseed=2, B=1, trust=True),
 }
 DEFAULT_WORKLOAD = "rmat23-ef256-u12"
 
@@ -454,8 +454,15 @@ def beyond_hbm(args):
     Xs = []
     budgets = (args.budget_gb, args.budget_gb * 0.85)
     infos = [cc.count_budget_plan(P, G, int(gb * 1e9)) for gb in budgets]
-    # one pinned host buffer for both runs (the larger need)
-    host = torch.empty(max(max(i["host_bytes"] for i in infos), 1), dtype=torch.uint8, pin_memory=True)
+    # one host buffer for both runs (the larger need): page-locked if the host allows it, else
+    # pageable (the copies are then staged by the runtime)
+    hbytes = max(max(i["host_bytes"] for i in infos), 1)
+    try:
+        host = torch.empty(hbytes, dtype=torch.uint8, pin_memory=True)
+        out["host_buffer"] = "page-locked"
+    except Exception:
+        host = torch.empty(hbytes, dtype=torch.uint8)
+        out["host_buffer"] = "pageable"
     for gb, info in zip(budgets, infos):
         X = torch.empty(1, dtype=torch.float64, device=dev)
         cc.count_budget(P, G, C, int(gb * 1e9), workspace=ws, host=host, out=X)  # warm-up
@@ -866,6 +873,33 @@ def summarize_pmc(args):
     print(json.dumps(res))
 
 
+def summarize_stats(args):
+    """rocprofv3 --kernel-trace --stats output (kernel_stats.csv) -> a markdown table of the kernels'
+    calls and durations, printed (copied into profiles/ with the command that made it)."""
+    f = glob.glob(os.path.join(args.stats_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit("no kernel_stats.csv under " + args.stats_dir)
+    rows = list(csv.DictReader(open(f[0])))
+    agg = {}
+    for r in rows:
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        name = re.sub(r"\(.*", "", name).replace("void ", "").strip()[:60]
+        name = re.sub(r"^.*::", "", name.split("<")[0]) + ("<" + name.split("<", 1)[1] if "<" in name else "")
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"]) / 1e6
+    total = sum(a[1] for a in agg.values())
+    print(f"# rocprofv3 kernel summary: {args.title}\n")
+    print("command (from the repository root on the MI355X box):\n  " + args.command + "\n")
+    print(f"bench.py kernel_hash of the split kernel's code and this template's plan constants: "
+          f"{kernel_hash(args.workload)}\n")
+    print("| kernel | calls | total ms | average ms | % |\n|---|---|---|---|---|")
+    for name, (calls, ms) in sorted(agg.items(), key=lambda x: -x[1][1]):
+        if ms < 0.01:
+            continue
+        print(f"| {name} | {calls} | {ms:.2f} | {ms / calls:.3f} | {100 * ms / total:.2f} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -893,15 +927,15 @@ def main():
                     help="requests of the capacity run and of each arrival rate (the same requests)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95],
                     help="Poisson arrival rates as fractions of the measured capacity")
-    ap.add_argument("--serve-mix", default="bench", choices=sorted(SERVE_MIXES))
-    ap.add_argument("--serve-cap", type=int, default=16,
+    ap.add_argument("--serve-mix", default="light", choices=sorted(SERVE_MIXES))
+    ap.add_argument("--serve-cap", type=int, default=4,
                     help="colourings of one request per batch (0: as many as fit)")
     ap.add_argument("--serve-fifo-load", type=float, default=0.95,
                     help="also run this load without the cap, first come first served (0: skip)")
     ap.add_argument("--only-serving", action="store_true", help="run only the serving leg")
     ap.add_argument("--only-budget", action="store_true",
                     help="count one colouring of --workload within --budget-gb of device workspace")
-    ap.add_argument("--budget-gb", type=float, default=260.0)
+    ap.add_argument("--budget-gb", type=float, default=290.0)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--budget-frac", type=float, default=0.9,
@@ -915,10 +949,16 @@ def main():
     ap.add_argument("--dispatch-map", default="",
                     help="write (bench run) or read (--summarize-pmc) the count's kernel sequence per colouring")
     ap.add_argument("--out", default="")
+    ap.add_argument("--summarize-stats", default="", metavar="DIR")
+    ap.add_argument("--title", default="")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args)
+        return 0
+    if args.summarize_stats:
+        args.stats_dir = args.summarize_stats
+        summarize_stats(args)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

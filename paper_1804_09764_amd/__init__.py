@@ -431,7 +431,10 @@ def count_budget(plan: Plan, graph: Graph, colours, budget: int, per_vertex: boo
     ws = (workspace or Workspace()).get(info["workspace_bytes"], dev)
     own_host = host is None
     if own_host:
-        host = torch.empty(max(info["host_bytes"], 1), dtype=torch.uint8, pin_memory=True)
+        try:
+            host = torch.empty(max(info["host_bytes"], 1), dtype=torch.uint8, pin_memory=True)
+        except Exception:  # the host refuses to lock that much: pageable, copies staged
+            host = torch.empty(max(info["host_bytes"], 1), dtype=torch.uint8)
     if host.is_cuda or host.numel() < info["host_bytes"]:
         raise ValueError("host must be a CPU tensor of at least host_bytes bytes")
     X = out if out is not None else torch.empty(B, dtype=torch.float64, device=dev)
