@@ -639,6 +639,8 @@ cc_status cc_count_projection(const cc_plan* P, const cc_graph* G, int32_t* clas
     return CC_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Splits [0, last] of plan P for one colouring on `st`: the per-entry neighbour colours, then
@@ -873,6 +875,8 @@ BudgetLayout budget_layout(const cc_plan* P, const cc_graph* G, size_t budget) {
 }
 
 }  // namespace
+
+extern "C" {
 
 cc_status cc_count(const cc_plan* P, const cc_graph* G, const uint8_t* colours_dev, int32_t B, void* ws_dev,
                    size_t ws_bytes, double* X_dev, double* vertex_dev, void* stream) {

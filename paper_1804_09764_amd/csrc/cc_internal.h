@@ -287,9 +287,9 @@ hipError_t launch_reduce_packed(const double* x, int64_t n, int B, double* parti
 // whose splits run the packed kernels; bar = 3 zeroed unsigned (barrier count, generation, error
 // flag), lds = dynamic LDS bytes for `waves` wavefronts per workgroup (the widest split's maps and
 // slices). Returns hipErrorCooperativeLaunchTooLarge when the grid cannot be co-resident.
-// Every split with p >= 2 takes JP tile elements per lane per pass and every split with p = 1 takes
-// kPersistentJ1 (StepParams.force_J), so that one kernel holds two variants only.
-constexpr int kPersistentJ1 = 8;
+// Every split with p >= 2 takes JP tile elements per lane per pass (StepParams.force_J), so that
+// the kernel holds one gather variant; a split with p = 1 keeps its own (StepParams.pJ), the colour
+// count variants being small.
 hipError_t launch_packed_persistent(const PSeg* segs, const PItemBlock* blocks, const PPhase* phases_host,
                                     const PPhase* phases_dev, int n_phases, int waves, int JP, size_t tab_doubles,
                                     size_t lds_wave, unsigned* bar, int n_cu, hipStream_t st);

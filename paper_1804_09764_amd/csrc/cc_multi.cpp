@@ -156,7 +156,7 @@ OneLaunch one_launch_layout(const cc_multi* M, const cc_graph* G, int32_t B) {
             const cc::Split& sp = P->splits[(size_t)st.split];
             nst = std::max(nst, cc::packed_stride((int64_t)B * sp.Cf));
             O.slot[i] = per_level[(size_t)lv]++;
-            const cc::StepParams h = tile_only_params(P, sp, G, B, sp.p >= 2 ? O.JP : cc::kPersistentJ1);
+            const cc::StepParams h = tile_only_params(P, sp, G, B, sp.p >= 2 ? O.JP : 0);
             O.tab_doubles = std::max(O.tab_doubles, (size_t)h.tab_doubles);
             O.lds_wave = std::max(O.lds_wave, (size_t)h.lds_wave);
             if (st.out < 0) continue;
@@ -397,7 +397,7 @@ cc_status cc_count_packed_multi_persistent(const cc_multi* M, const cc_graph* G,
             double* part = partial + (size_t)O.slot[i] * (size_t)G->n_chunks * (size_t)L.nstride;
             cc::StepParams h = packed_step_params(P, G, sp, PIds{S.act, S.pas, S.out}, cpk, arena, L, part,
                                                   roots + (size_t)S.plan * root_rows, B);
-            h.force_J = sp.p >= 2 ? O.JP : cc::kPersistentJ1;
+            h.force_J = sp.p >= 2 ? O.JP : 0;
             cc::packed_tile(&h);
             h.lds_wave = (int)O.lds_wave;  // every wavefront's slice has the widest split's size
             M->pseg_host[i].S = h;

@@ -33,28 +33,42 @@ struct PMaps {
 
 // Colours of the 64 entries of a CSR block for the tile's colourings, staged in LDS:
 // cs[i * bt + bl] = col_{b0 + bl}(u_i). Lane i copies the colours of its own entry, so a block's
-// colours arrive in one round trip instead of one per entry.
+// colours arrive in one round trip instead of one per entry. Every load of a lane is issued before
+// its first store (loads past the tile's colourings re-read its last word and are not stored), and
+// the words are held in plain registers: an array here would be placed in scratch memory.
+typedef unsigned cc_u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ inline void stage_colours(const StepParams& S, int uvec, int cnt, int b0, int nb, uint8_t* cs, int lane) {
     wave_sync_lds();  // earlier reads of the stage are done
     if (lane < cnt) {
         const uint8_t* src = S.colour + (int64_t)uvec * S.B + b0;
         uint8_t* dst = cs + lane * S.bt;
-        if (((S.B | b0 | nb | S.bt) & 15) == 0) {  // 16 colourings per load, all loads in flight
-            uint4 w[kWave / 16];
-#pragma unroll
-            for (int q = 0; q < kWave / 16; ++q)
-                if (16 * q < nb) w[q] = *reinterpret_cast<const uint4*>(src + 16 * q);
-#pragma unroll
-            for (int q = 0; q < kWave / 16; ++q)
-                if (16 * q < nb) *reinterpret_cast<uint4*>(dst + 16 * q) = w[q];
+        if (((S.B | b0 | nb | S.bt) & 15) == 0) {  // 16 colourings per load (nb <= 64)
+            const int last = (nb >> 4) - 1;
+            const cc_u32x4* s4 = reinterpret_cast<const cc_u32x4*>(src);
+            cc_u32x4* d4 = reinterpret_cast<cc_u32x4*>(dst);
+            const cc_u32x4 w0 = s4[0];
+            const cc_u32x4 w1 = s4[last < 1 ? last : 1];
+            const cc_u32x4 w2 = s4[last < 2 ? last : 2];
+            const cc_u32x4 w3 = s4[last < 3 ? last : 3];
+            d4[0] = w0;
+            if (last >= 1) d4[1] = w1;
+            if (last >= 2) d4[2] = w2;
+            if (last >= 3) d4[3] = w3;
         } else if (((S.B | b0 | nb | S.bt) & 3) == 0) {  // four colourings per load
-            uint32_t w[kWave / 4];
-#pragma unroll
-            for (int q = 0; q < kWave / 4; ++q)
-                if (4 * q < nb) w[q] = *reinterpret_cast<const uint32_t*>(src + 4 * q);
-#pragma unroll
-            for (int q = 0; q < kWave / 4; ++q)
-                if (4 * q < nb) *reinterpret_cast<uint32_t*>(dst + 4 * q) = w[q];
+            const int last = (nb >> 2) - 1;
+            const uint32_t* s1 = reinterpret_cast<const uint32_t*>(src);
+            uint32_t* d1 = reinterpret_cast<uint32_t*>(dst);
+            for (int q0 = 0; q0 <= last; q0 += 4) {
+                const uint32_t w0 = s1[q0];
+                const uint32_t w1 = s1[q0 + 1 <= last ? q0 + 1 : last];
+                const uint32_t w2 = s1[q0 + 2 <= last ? q0 + 2 : last];
+                const uint32_t w3 = s1[q0 + 3 <= last ? q0 + 3 : last];
+                d1[q0] = w0;
+                if (q0 + 1 <= last) d1[q0 + 1] = w1;
+                if (q0 + 2 <= last) d1[q0 + 2] = w2;
+                if (q0 + 3 <= last) d1[q0 + 3] = w3;
+            }
         } else {
             for (int q = 0; q < nb; ++q) dst[q] = src[q];
         }

@@ -250,7 +250,10 @@ __global__ __launch_bounds__(256, 3) void k_pmulti(const PSeg* __restrict__ segs
             if (wib < ib.count) {
                 double* Ash = N + S.a_off;
                 if (finish) do_phub(S, ib.first + wib, N, Ash, M, lane);
-                else if (segs[seg].p1) do_ptask<kPersistentJ1, true>(S, ib.first + wib, N, Ash, M, lane);
+                else if (segs[seg].p1) {
+                    if (__builtin_amdgcn_readfirstlane(S.pJ) <= 4) do_ptask<4, true>(S, ib.first + wib, N, Ash, M, lane);
+                    else do_ptask<8, true>(S, ib.first + wib, N, Ash, M, lane);
+                }
                 else do_ptask<JP, false>(S, ib.first + wib, N, Ash, M, lane);
             }
         }
