@@ -284,8 +284,8 @@ hipError_t launch_transpose_colours(const uint8_t* in, int64_t n, int B, uint8_t
 int packed_reduce_blocks(int64_t n);
 hipError_t launch_reduce_packed(const double* x, int64_t n, int B, double* partial, double* out, hipStream_t st);
 // the persistent multi-template launch: phases[0 .. n_phases) in order over the item blocks, all of
-// whose splits run the packed kernels; bar = 3 zeroed unsigned (barrier count, generation, error
-// flag), lds = dynamic LDS bytes for `waves` wavefronts per workgroup (the widest split's maps and
+// whose splits run the packed kernels; bar = 3 + n_phases zeroed unsigned (barrier count,
+// generation, error flag, one item-block counter per phase), lds = dynamic LDS bytes for `waves` wavefronts per workgroup (the widest split's maps and
 // slices). Returns hipErrorCooperativeLaunchTooLarge when the grid cannot be co-resident.
 // Every split with p >= 2 takes JP tile elements per lane per pass (StepParams.force_J), so that
 // the kernel holds one gather variant; a split with p = 1 keeps its own (StepParams.pJ), the colour

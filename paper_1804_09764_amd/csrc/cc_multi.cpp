@@ -182,8 +182,14 @@ OneLaunch one_launch_layout(const cc_multi* M, const cc_graph* G, int32_t B) {
     for (int c : per_level) O.slots = std::max(O.slots, c);
     while (O.waves > 1 && (O.tab_doubles + O.lds_wave * (size_t)O.waves) * sizeof(double) > 64 * 1024) O.waves >>= 1;
     const int64_t tasks = G->n_chunks + G->n_ranges;
-    for (size_t i = 0; i < M->steps.size(); ++i)
-        O.n_blocks += (tasks + O.waves - 1) / O.waves + (G->n_hubs + O.waves - 1) / O.waves;
+    for (size_t i = 0; i < M->steps.size(); ++i) {
+        const cc_multi::Step& st = M->steps[i];
+        const cc_plan* P = M->plans[(size_t)st.plan];
+        const cc::Split& sp = P->splits[(size_t)st.split];
+        const cc::StepParams h = tile_only_params(P, sp, G, B, sp.p >= 2 ? O.JP : 0);
+        const int64_t tiles = (B + h.bt - 1) / h.bt;
+        O.n_blocks += (tasks * tiles + O.waves - 1) / O.waves + (G->n_hubs * tiles + O.waves - 1) / O.waves;
+    }
     const int64_t np = (int64_t)M->plans.size();
     L.nstride = nst;
     L.arena_off = 0;
@@ -195,7 +201,8 @@ OneLaunch one_launch_layout(const cc_multi* M, const cc_graph* G, int32_t B) {
     O.block_off = align256(O.seg_off + M->steps.size() * sizeof(cc::PSeg));
     O.phase_off = align256(O.block_off + (size_t)O.n_blocks * sizeof(cc::PItemBlock));
     O.bar_off = align256(O.phase_off + (size_t)(2 * O.n_levels) * sizeof(cc::PPhase));
-    O.total = align256(O.bar_off + 4 * sizeof(unsigned));
+    // barrier count, generation, error flag, then one item-block counter per phase
+    O.total = align256(O.bar_off + (size_t)(3 + 2 * O.n_levels) * sizeof(unsigned));
     L.total = O.total;
     return O;
 }
@@ -409,9 +416,11 @@ cc_status cc_count_packed_multi_persistent(const cc_multi* M, const cc_graph* G,
         for (int lv = 0; lv < O.n_levels; ++lv) {
             for (int phase = 0; phase < 2; ++phase) {
                 cc::PPhase ph{(int64_t)M->pblock_host.size(), 0};
-                const int64_t items = phase == 0 ? tasks : G->n_hubs;
                 for (size_t i = 0; i < M->steps.size(); ++i) {
                     if (O.level[i] != lv) continue;
+                    // items: (task or cut row, colouring tile) pairs
+                    const cc::StepParams& h = M->pseg_host[i].S;
+                    const int64_t items = (phase == 0 ? tasks : G->n_hubs) * (int64_t)((h.B + h.bt - 1) / h.bt);
                     for (int64_t f = 0; f < items; f += O.waves)
                         M->pblock_host.push_back(
                             cc::PItemBlock{(int32_t)i, (int32_t)std::min<int64_t>(O.waves, items - f), f});
@@ -443,7 +452,7 @@ cc_status cc_count_packed_multi_persistent(const cc_multi* M, const cc_graph* G,
     if (e == hipSuccess)
         e = hipMemcpyAsync(phase_dev, M->pphase_host.data(), M->pphase_host.size() * sizeof(cc::PPhase),
                            hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = cc::launch_fill_u32(bar, 4, 0u, st);
+    if (e == hipSuccess) e = cc::launch_fill_u32(bar, 3 + (int64_t)M->pphase_host.size(), 0u, st);
     if (e == hipSuccess)
         e = cc::launch_packed_persistent(seg_dev, block_dev, M->pphase_host.data(), phase_dev,
                                          (int)M->pphase_host.size(), O.waves, O.JP, O.tab_doubles, O.lds_wave, bar,

@@ -257,62 +257,62 @@ __device__ __forceinline__ void pneighbours(const StepParams& S, int64_t beg, in
     else pgather<J>(S, beg, end, cvrow, b0, nb, N, fml, reinterpret_cast<int16_t*>(N + S.tg_off), cs, lane);
 }
 
+// colouring tiles of a row: the work items of a packed split are (task, tile) and (cut row, tile)
+// pairs, so that the tiles of one task run on different wavefronts
+__device__ __forceinline__ int ptiles(const StepParams& S) { return (S.B + S.bt - 1) / S.bt; }
+
+// light row v, colourings [b0, b0 + nb): neighbour sum, then the combine
 template <int J, bool P1>
-__device__ void plight_row(const StepParams& S, int v, double* N, double* Ash, const PMaps& M, int lane) {
+__device__ void plight_row(const StepParams& S, int v, int b0, int nb, double* N, double* Ash, const PMaps& M,
+                           int lane) {
     const int64_t beg = S.row_ptr[v];
     const int64_t end = S.row_ptr[v + 1];
-    const uint8_t* cvall = S.colour + (int64_t)v * S.B;
-    for (int b0 = 0; b0 < S.B; b0 += S.bt) {
-        const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
-        pstage_a(S, v, b0, nb, Ash, lane);
-        for (int i = lane; i < nb * S.Cf; i += kWave) N[i] = 0.0;
-        wave_sync_lds();
-        if (beg < end) pneighbours<J, P1>(S, beg, end, cvall + b0, b0, nb, N, M, lane);
-        wave_sync_lds();
-        pcombine(S, v, cvall + b0, b0, nb, N, Ash, M, lane);
-        wave_sync_lds();
-    }
+    const uint8_t* cvrow = S.colour + (int64_t)v * S.B + b0;
+    pstage_a(S, v, b0, nb, Ash, lane);
+    for (int i = lane; i < nb * S.Cf; i += kWave) N[i] = 0.0;
+    wave_sync_lds();
+    if (beg < end) pneighbours<J, P1>(S, beg, end, cvrow, b0, nb, N, M, lane);
+    wave_sync_lds();
+    pcombine(S, v, cvrow, b0, nb, N, Ash, M, lane);
+    wave_sync_lds();
 }
 
-// task t: a chunk of a cut row (partial rows of all colourings to scratch) or a range of light rows
+// colourings [b0, b0 + bt) of task t: a chunk of a cut row (partial rows to scratch) or a range
+// of light rows
 template <int J, bool P1>
-__device__ void do_ptask(const StepParams& S, int64_t t, double* N, double* Ash, const PMaps& M, int lane) {
+__device__ void do_ptask(const StepParams& S, int64_t t, int b0, double* N, double* Ash, const PMaps& M, int lane) {
+    const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
     if (t < S.n_chunks) {
         const ChunkItem ch = S.chunks[t];
         const int v = __builtin_amdgcn_readfirstlane(ch.v);
-        const uint8_t* cvall = S.colour + (int64_t)v * S.B;
-        double* prow = S.partial + t * S.nstride;
-        for (int b0 = 0; b0 < S.B; b0 += S.bt) {
-            const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
-            for (int i = lane; i < nb * S.Cf; i += kWave) N[i] = 0.0;
-            wave_sync_lds();
-            pneighbours<J, P1>(S, ch.beg, ch.beg + ch.len, cvall + b0, b0, nb, N, M, lane);
-            wave_sync_lds();
-            for (int i = lane; i < nb * S.Cf; i += kWave) prow[(int64_t)b0 * S.Cf + i] = N[i];
-            wave_sync_lds();
-        }
+        double* prow = S.partial + t * S.nstride + (int64_t)b0 * S.Cf;
+        for (int i = lane; i < nb * S.Cf; i += kWave) N[i] = 0.0;
+        wave_sync_lds();
+        pneighbours<J, P1>(S, ch.beg, ch.beg + ch.len, S.colour + (int64_t)v * S.B + b0, b0, nb, N, M, lane);
+        wave_sync_lds();
+        for (int i = lane; i < nb * S.Cf; i += kWave) prow[i] = N[i];
+        wave_sync_lds();
     } else {
         const int64_t r = t - S.n_chunks;
         const int i0 = S.light_start[r], i1 = S.light_start[r + 1];
-        for (int i = i0; i < i1; ++i) plight_row<J, P1>(S, S.light[i], N, Ash, M, lane);
+        for (int i = i0; i < i1; ++i) plight_row<J, P1>(S, S.light[i], b0, nb, N, Ash, M, lane);
     }
 }
 
-// cut row t: chunk partials added in the fixed blocked order, then the combine
-__device__ inline void do_phub(const StepParams& S, int64_t t, double* N, double* Ash, const PMaps& M, int lane) {
+// colourings [b0, b0 + bt) of cut row t: the row's chunk partials added in the fixed blocked order,
+// then the combine
+__device__ inline void do_phub(const StepParams& S, int64_t t, int b0, double* N, double* Ash, const PMaps& M,
+                               int lane) {
     const HubItem h = S.hubs[t];
-    const uint8_t* cvall = S.colour + (int64_t)h.v * S.B;
-    for (int b0 = 0; b0 < S.B; b0 += S.bt) {
-        const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
-        pstage_a(S, h.v, b0, nb, Ash, lane);
-        for (int i = lane; i < nb * S.Cf; i += kWave) {
-            const double* pp = S.partial + h.first_chunk * S.nstride + (int64_t)b0 * S.Cf + i;
-            N[i] = blocked_sum(h.n_chunks, [&](int c) { return pp[(int64_t)c * S.nstride]; });
-        }
-        wave_sync_lds();
-        pcombine(S, h.v, cvall + b0, b0, nb, N, Ash, M, lane);
-        wave_sync_lds();
+    const int nb = (S.B - b0 < S.bt) ? S.B - b0 : S.bt;
+    pstage_a(S, h.v, b0, nb, Ash, lane);
+    for (int i = lane; i < nb * S.Cf; i += kWave) {
+        const double* pp = S.partial + h.first_chunk * S.nstride + (int64_t)b0 * S.Cf + i;
+        N[i] = blocked_sum(h.n_chunks, [&](int c) { return pp[(int64_t)c * S.nstride]; });
     }
+    wave_sync_lds();
+    pcombine(S, h.v, S.colour + (int64_t)h.v * S.B + b0, b0, nb, N, Ash, M, lane);
+    wave_sync_lds();
 }
 
 // block-shared maps, copied from the plan constants: the split list (a >= 2, u32), then FM

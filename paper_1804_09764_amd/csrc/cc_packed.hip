@@ -21,10 +21,16 @@ __global__ __launch_bounds__(256) void k_psplit(StepParams S) {
     const int wib = threadIdx.x / kWave;
     double* N = lds + S.tab_doubles + (int64_t)wib * S.lds_wave;
     double* Ash = N + S.a_off;
+    // the wavefronts form groups of `tiles`, one per colouring tile; the groups take the tasks
+    // round-robin (the launch has at least `tiles` wavefronts)
+    const int tiles = ptiles(S);
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * S.waves_per_block + wib);
+    const int groups = (int)(gridDim.x * S.waves_per_block) / tiles;
+    const int g = w / tiles;
+    const int b0 = (w - g * tiles) * S.bt;
+    if (g >= groups) return;
     const int64_t n_tasks = S.n_chunks + S.n_ranges;
-    const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves)
-        do_ptask<J, P1>(S, t, N, Ash, M, lane);
+    for (int64_t t = g; t < n_tasks; t += groups) do_ptask<J, P1>(S, t, b0, N, Ash, M, lane);
 }
 
 __global__ __launch_bounds__(256) void k_phub(StepParams S) {
@@ -35,9 +41,13 @@ __global__ __launch_bounds__(256) void k_phub(StepParams S) {
     const int wib = threadIdx.x / kWave;
     double* N = lds + S.tab_doubles + (int64_t)wib * S.lds_wave;
     double* Ash = N + S.a_off;
-    const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves)
-        do_phub(S, t, N, Ash, M, lane);
+    const int tiles = ptiles(S);
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * S.waves_per_block + wib);
+    const int groups = (int)(gridDim.x * S.waves_per_block) / tiles;
+    const int g = w / tiles;
+    const int b0 = (w - g * tiles) * S.bt;
+    if (g >= groups) return;
+    for (int64_t t = g; t < S.n_hubs; t += groups) do_phub(S, t, b0, N, Ash, M, lane);
 }
 
 // [B][n] -> [n][B] bytes through 64 x 64 LDS tiles
@@ -150,7 +160,8 @@ hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
     if (err != hipSuccess) return err;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const int64_t total = S.n_chunks + S.n_ranges;
+    const int64_t tiles = (S.B + S.bt - 1) / S.bt;
+    const int64_t total = (S.n_chunks + S.n_ranges) * tiles;
     int64_t blocks = (int64_t)per_cu * n_cu;
     const int64_t need = (total + w - 1) / w;
     if (blocks > need) blocks = need;
@@ -172,7 +183,7 @@ hipError_t launch_packed_split(StepParams S, int n_cu, hipStream_t st, hipEvent_
         if (err != hipSuccess) return err;
         if (per_cu2 < 1) return hipErrorInvalidConfiguration;
         int64_t b2 = (int64_t)per_cu2 * n_cu;
-        const int64_t need2 = (S.n_hubs + w - 1) / w;
+        const int64_t need2 = (S.n_hubs * tiles + w - 1) / w;
         if (b2 > need2) b2 = need2;
         hipLaunchKernelGGL(k_phub, dim3((unsigned)b2), dim3(threads), lds, st, S);
         err = hipGetLastError();
@@ -217,9 +228,14 @@ __device__ void grid_barrier(unsigned* bar, unsigned nblocks) {
     __syncthreads();
 }
 
-// The phases in order (even: the tasks of a dependency level, odd: its cut-row finishes); a
-// workgroup takes item blocks round-robin, stages the block's split maps in LDS when the split
-// changes, and each of its wavefronts runs one item of the block.
+// The phases in order (even: the tasks of a dependency level, odd: its cut-row finishes; an item is
+// one colouring tile of a task or cut row). Item
+// blocks are taken from a per-phase counter (bar[3 + ph], zero at launch): a workgroup that ends
+// its block early takes the next one, so the phase ends about one block after the first
+// workgroup runs out of work, whatever the spread of item costs (light-row ranges of many small
+// rows cost several times a range of one large row). The workgroup stages the block's split maps
+// in LDS when the split changes, and each of its wavefronts runs one item of the block. Which
+// workgroup runs an item changes nothing in its arithmetic.
 template <int JP>
 __global__ __launch_bounds__(256, 3) void k_pmulti(const PSeg* __restrict__ segs, const PItemBlock* __restrict__ blocks,
                                                 const PPhase* __restrict__ phases, int n_phases, int tab_doubles,
@@ -233,15 +249,21 @@ __global__ __launch_bounds__(256, 3) void k_pmulti(const PSeg* __restrict__ segs
     // the current split's arguments, staged in LDS with its maps (read from HBM they measured
     // 25 % slower: fields are read inside the neighbour loops)
     __shared__ StepParams Ssh;
+    __shared__ unsigned next;
     for (int ph = 0; ph < n_phases; ++ph) {
         const PPhase P = phases[ph];
         const bool finish = (ph & 1) != 0;
-        for (int64_t b = blockIdx.x; b < P.n_blocks; b += gridDim.x) {
+        for (;;) {
+            if (threadIdx.x == 0)
+                next = __hip_atomic_fetch_add(bar + 3 + ph, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int64_t b = next;
+            __syncthreads();  // every wavefront has read `next` before it is written again
+            if (b >= P.n_blocks) break;
             const PItemBlock ib = blocks[P.first_block + b];
             const int seg = __builtin_amdgcn_readfirstlane(ib.seg);
             if (seg != staged) {
-                __syncthreads();  // the workgroup is done with the previous maps
-                M = stage_maps(segs[seg].S, lds);
+                M = stage_maps(segs[seg].S, lds);  // the workgroup is past the previous block
                 if (threadIdx.x == 0) Ssh = segs[seg].S;
                 __syncthreads();
                 staged = seg;
@@ -249,12 +271,15 @@ __global__ __launch_bounds__(256, 3) void k_pmulti(const PSeg* __restrict__ segs
             const StepParams& S = Ssh;
             if (wib < ib.count) {
                 double* Ash = N + S.a_off;
-                if (finish) do_phub(S, ib.first + wib, N, Ash, M, lane);
+                const int tiles = ptiles(S);
+                const int64_t item = ib.first + __builtin_amdgcn_readfirstlane(wib);
+                const int64_t t = item / tiles;
+                const int b0 = (int)(item - t * tiles) * S.bt;
+                if (finish) do_phub(S, t, b0, N, Ash, M, lane);
                 else if (segs[seg].p1) {
-                    if (__builtin_amdgcn_readfirstlane(S.pJ) <= 4) do_ptask<4, true>(S, ib.first + wib, N, Ash, M, lane);
-                    else do_ptask<8, true>(S, ib.first + wib, N, Ash, M, lane);
-                }
-                else do_ptask<JP, false>(S, ib.first + wib, N, Ash, M, lane);
+                    if (__builtin_amdgcn_readfirstlane(S.pJ) <= 4) do_ptask<4, true>(S, t, b0, N, Ash, M, lane);
+                    else do_ptask<8, true>(S, t, b0, N, Ash, M, lane);
+                } else do_ptask<JP, false>(S, t, b0, N, Ash, M, lane);
             }
         }
         if (ph + 1 < n_phases) grid_barrier(bar, gridDim.x);
