@@ -482,6 +482,58 @@ def beyond_hbm(args):
     return out
 
 
+def packed_compare(args):
+    """Packed against plain on a workload's own graph and template: the largest number of
+    colourings (up to the workload's colourings per step) whose packed count fits in 85 % of the
+    free HBM, counted once packed (one cc_count_packed) and once plain (one cc_count of the same
+    colourings), after a warm-up of each. Reports time per colouring and whether the counts agree
+    (exact below 2^53, 1e-12 relative above). Answers whether packing the colourings of the
+    headline step would pay, with or without a device budget."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1804_09764_amd as cc
+    W = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    rp_d, col_d = inputs.rmat_graph_gpu(W["scale"], W["ef"], W["gseed"], device=dev)
+    G = cc.Graph(rp_d, col_d, trust=W["trust"])
+    P = cc.Plan(inputs.pruefer_tree(W["k"], W["tseed"]))
+    free = torch.cuda.mem_get_info(dev)[0]
+    need = {b: cc.count_packed_workspace_bytes(P, G, b) for b in range(1, W["B"] + 1)}
+    fits = [b for b in need if need[b] <= 0.85 * free]
+    out = {"workload": args.workload, "n": G.n, "nnz": G.nnz, "colourings_per_step": W["B"],
+           "packed_workspace_GB": {str(b): need[b] / 1e9 for b in need},
+           "plain_workspace_GB": cc.count_workspace_bytes(P, G) / 1e9, "free_GB": free / 1e9}
+    if not fits:
+        out["fits"] = False
+        return out
+    B = max(fits)
+    C = cc.colour(G, W["k"], seed=args.seed, first_iter=0, B=B)
+    Xp = torch.empty(B, dtype=torch.float64, device=dev)
+    Xq = torch.empty(B, dtype=torch.float64, device=dev)
+    res = {}
+    for name, fn in (("plain", lambda ws: cc.count(P, G, C, workspace=ws, out=Xp)),
+                     ("packed", lambda ws: cc.count_packed(P, G, C, workspace=ws, out=Xq))):
+        ws = cc.Workspace()
+        fn(ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(ws)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) * 1e3 / B
+        print(f"[bench] {name}: {res[name]:.1f} ms per colouring ({B} colourings)", file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+    xp, xq = Xp.cpu().numpy(), Xq.cpu().numpy()
+    small = xp < 2.0 ** 53
+    agree = bool(np.array_equal(xp[small], xq[small]) and np.all(np.abs(xq - xp)[~small] <= 1e-12 * xp[~small]))
+    out.update({"fits": True, "colourings": B, "plain_ms_per_colouring": res["plain"],
+                "packed_ms_per_colouring": res["packed"], "packed_over_plain": res["packed"] / res["plain"],
+                "agree": agree})
+    return out
+
+
 def budget_leg(P, G, k, args, full_bytes, ws):
     """One colouring of the headline workload counted within a device budget of budget_frac of the
     plain count's workspace (cc_count_budget: tables idle across the peak wait in pinned host
@@ -525,8 +577,9 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
               holding all 64 colourings, and the table of each distinct rooted sub-template
               computed once for all trees (exact below 2^53, 1e-12 relative above, against plain);
     packed_per_tree = one cc_count_packed call per tree (no sharing across trees);
-    instances_persistent / instances_levels = the 704 (tree, colouring) instances in one persistent
-              launch / one launch per dependency level (bit-identical to plain).
+    instances_persistent / instances_levels (with --instances) = the 704 (tree, colouring)
+              instances in one persistent launch / one launch per dependency level (bit-identical
+              to plain).
     All legs are credited with the same units: the trees' reference-partition units x 64."""
     import numpy as np
     import torch
@@ -580,15 +633,17 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
     def persistent_multi():
         multi.count(Gt, C, workspace=wsq, out=Xq, persistent=True)
 
+    legs = [("plain", plain), ("batched", shared), ("batched_persistent", persistent_multi),
+            ("packed_per_tree", packed)]
     Xb = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
     inst = [(P, G, C[b], Xb[t, b:b + 1], None) for t, P in enumerate(plans) for b in range(B)]
-    persistent = cc.Batch(inst)
-    levels = cc.Batch(inst, levels=True)
-    wsb = cc.Workspace()
+    if args.instances:
+        persistent = cc.Batch(inst)
+        levels = cc.Batch(inst, levels=True)
+        wsb = cc.Workspace()
+        legs += [("instances_persistent", lambda: persistent.run(wsb)), ("instances_levels", lambda: levels.run(wsb))]
     res = {}
-    for name, fn in (("plain", plain), ("batched", shared), ("batched_persistent", persistent_multi),
-                     ("packed_per_tree", packed),
-                     ("instances_persistent", lambda: persistent.run(wsb)), ("instances_levels", lambda: levels.run(wsb))):
+    for name, fn in legs:
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -608,7 +663,7 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
     def matches(x):
         return bool(np.array_equal(x[small], xp[small]) and
                     (np.all(np.abs(x[~small] - xp[~small]) <= 1e-12 * xp[~small]) if (~small).any() else True))
-    return {"workload": "rmat18-ef16-trees7x64",
+    out = {"workload": "rmat18-ef16-trees7x64",
             "graph": "R-MAT scale 18 edge factor 16 seed 2", "n": n, "nnz": nnz,
             "templates": "all 11 trees with 7 vertices", "colourings": B, "instances": len(inst),
             "units": units,
@@ -631,16 +686,19 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
             "packed_per_tree": {"value": units / res["packed_per_tree"], "ms": res["packed_per_tree"] * 1e3,
                                 "matches_plain": matches(Xk.cpu().numpy()),
                                 "launch": "one packed count per tree"},
-            "instances_persistent": {"value": units / res["instances_persistent"],
-                                     "ms": res["instances_persistent"] * 1e3,
-                                     "equal_to_plain": res["instances_persistent_equal"],
-                                     "launch": "704 instances, one persistent launch"},
-            "instances_levels": {"value": units / res["instances_levels"], "ms": res["instances_levels"] * 1e3,
-                                 "equal_to_plain": res["instances_levels_equal"],
-                                 "launch": "704 instances, one launch per dependency level"},
             "workspace_GB": {"batched": multi.workspace_bytes(G, B) / 1e9,
-                             "packed_per_tree": max(cc.count_packed_workspace_bytes(p, G, B) for p in plans) / 1e9,
-                             "instances": persistent.workspace_bytes / 1e9}}
+                             "batched_persistent": multi.workspace_bytes(G, B, persistent=True) / 1e9,
+                             "packed_per_tree": max(cc.count_packed_workspace_bytes(p, G, B) for p in plans) / 1e9}}
+    if args.instances:
+        out["instances_persistent"] = {"value": units / res["instances_persistent"],
+                                       "ms": res["instances_persistent"] * 1e3,
+                                       "equal_to_plain": res["instances_persistent_equal"],
+                                       "launch": "704 instances, one persistent launch"}
+        out["instances_levels"] = {"value": units / res["instances_levels"], "ms": res["instances_levels"] * 1e3,
+                                   "equal_to_plain": res["instances_levels_equal"],
+                                   "launch": "704 instances, one launch per dependency level"}
+        out["workspace_GB"]["instances"] = persistent.workspace_bytes / 1e9
+    return out
 
 
 SERVE_POOL = [(16 + (i % 7), (8, 16, 32)[i % 3], 100 + i) for i in range(16)]  # (scale, edge factor, seed)
@@ -685,7 +743,8 @@ def serving_leg(args):
     """Continuous-batching server over 16 resident R-MAT graphs (scale 16..22, edge factor 8..32).
 
     One request mix (seed 9) throughout: first the capacity, with all of its requests queued at
-    once; then the same requests with Poisson arrivals at 50 %, 80 % and 95 % of that capacity.
+    once; then the same requests with Poisson arrivals at fractions of that capacity (--serve-loads,
+    80 % and 95 % by default).
     Reports served CSEU/s and p50/p99 latency (arrival to result) per load, with each request's
     colourings capped per batch (slot_colourings) so that small requests share the batches of large
     ones; at the highest load the same arrivals also run first come, first served without the cap,
@@ -925,7 +984,7 @@ def main():
                     help="print a line after each timed step (synchronises between steps)")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests of the capacity run and of each arrival rate (the same requests)")
-    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95],
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.8, 0.95],
                     help="Poisson arrival rates as fractions of the measured capacity")
     ap.add_argument("--serve-mix", default="light", choices=sorted(SERVE_MIXES))
     ap.add_argument("--serve-cap", type=int, default=4,
@@ -937,7 +996,12 @@ def main():
                     help="count one colouring of --workload within --budget-gb of device workspace")
     ap.add_argument("--budget-gb", type=float, default=290.0)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
-    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--cpu-seconds", type=float, default=6.0)
+    ap.add_argument("--instances", action="store_true",
+                    help="also time the instance batches (704 instances in one or a few launches)")
+    ap.add_argument("--only-packed-compare", action="store_true",
+                    help="packed counts of the largest colouring batch that fits against plain counts "
+                         "of the same colourings, on --workload")
     ap.add_argument("--budget-frac", type=float, default=0.9,
                     help="also count one colouring within this fraction of the plain workspace (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -980,6 +1044,9 @@ def main():
         return 0
     if args.only_serving:
         print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return 0
+    if args.only_packed_compare:
+        print(json.dumps({"packed_compare": packed_compare(args)}), flush=True)
         return 0
     if args.only_batched:
         # the batched leg alone (for profiling its kernels); not the benchmark line

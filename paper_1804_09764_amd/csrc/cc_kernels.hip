@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256, (NARROW == 16 ? 4 : 1)) void k_split(StepParam
     double* Ash = N + S.a_off;
     const int64_t n_tasks = S.n_chunks + S.n_ranges;
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < n_tasks; t += n_waves)
+    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + __builtin_amdgcn_readfirstlane(wib); t < n_tasks; t += n_waves)
         do_task<J, NARROW>(S, t, N, Ash, lane);
 }
 
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_hub_finish(StepParams S) {
     double* N = lds + (int64_t)wib * S.lds_wave;
     double* Ash = N + S.a_off;
     const int64_t n_waves = (int64_t)gridDim.x * S.waves_per_block;
-    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + wib; t < S.n_hubs; t += n_waves)
+    for (int64_t t = (int64_t)blockIdx.x * S.waves_per_block + __builtin_amdgcn_readfirstlane(wib); t < S.n_hubs; t += n_waves)
         do_hub(S, t, N, Ash, lane);
 }
 
