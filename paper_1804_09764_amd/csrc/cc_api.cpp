@@ -84,7 +84,7 @@ std::vector<int> projection_plan(const cc_plan* P, const cc_graph* G, int64_t n_
         } else {
             cls = (int)std::max(1.0, std::min((double)k, std::floor(arena_bytes / per_class)));
             const int passes = (k + cls - 1) / cls;
-            if (sp.lines_need < 1.3 * (sp.Wn_pad / 16.0)) continue;
+            if (sp.lines_need < 1.2 * (sp.Wn_pad / 16.0)) continue;
             const double saved = (double)G->nnz * (k - 1) / k * 128.0 * (sp.lines_need - sp.Wn_pad / 16.0);
             const double cost = (double)G->n * sizeof(double) *
                                 ((double)passes * cc::pad_stride(sp.Wp) + (double)(k - 1) * sp.Wn_pad);

@@ -147,7 +147,9 @@ __device__ __forceinline__ void consume_batch(int b, int cnt, int sc, int& cur, 
 
 template <int J>
 __device__ void gather_fold(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, int lane) {
-    constexpr int D = (J >= 6) ? 1 : (J >= 4) ? 2 : 4;  // rows per batch: two batches within the VGPR budget
+    // rows per batch (two batches in flight): from 4 doubles per lane one row, which keeps the
+    // 4-double variant at five wavefronts per SIMD (two rows: four, and 8 % slower)
+    constexpr int D = (J >= 4) ? 1 : 4;
     const int k = S.k;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // the passive rows: the table itself, or in a projected pass the copy for this centre colour
