@@ -633,8 +633,10 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
     def persistent_multi():
         multi.count(Gt, C, workspace=wsq, out=Xq, persistent=True)
 
-    legs = [("plain", plain), ("batched", shared), ("batched_persistent", persistent_multi),
-            ("packed_per_tree", packed)]
+    legs = [("plain", plain), ("batched", shared)]
+    if not args.no_persistent:
+        legs.append(("batched_persistent", persistent_multi))
+    legs.append(("packed_per_tree", packed))
     Xb = torch.empty((len(plans), B), dtype=torch.float64, device=dev)
     inst = [(P, G, C[b], Xb[t, b:b + 1], None) for t, P in enumerate(plans) for b in range(B)]
     if args.instances:
@@ -677,18 +679,19 @@ def batched_vs_plain(args, reps: int = 2, inst_reps: int = 1):
                         "autotuned": {"hub_threshold": rec.hub_threshold, "chunk": rec.chunk,
                                       "packed_tile": rec.packed_tile, "ms": rec.ms, "default_ms": rec.default_ms,
                                       "candidates": len(rec.timings), "tuning_s": tune_s}},
-            "batched_persistent": {"value": units / res["batched_persistent"], "ms": res["batched_persistent"] * 1e3,
-                                   "speedup_vs_plain": res["plain"] / res["batched_persistent"],
-                                   "equal_to_batched": bool(torch.equal(Xq, Xm)),
-                                   "launch": "the same count in one persistent cooperative launch over (split, "
-                                             "task or cut row, colouring tile) items, dependency levels separated "
-                                             "by a device-wide barrier"},
             "packed_per_tree": {"value": units / res["packed_per_tree"], "ms": res["packed_per_tree"] * 1e3,
                                 "matches_plain": matches(Xk.cpu().numpy()),
                                 "launch": "one packed count per tree"},
             "workspace_GB": {"batched": multi.workspace_bytes(G, B) / 1e9,
                              "batched_persistent": multi.workspace_bytes(G, B, persistent=True) / 1e9,
                              "packed_per_tree": max(cc.count_packed_workspace_bytes(p, G, B) for p in plans) / 1e9}}
+    if not args.no_persistent:
+        out["batched_persistent"] = {"value": units / res["batched_persistent"], "ms": res["batched_persistent"] * 1e3,
+                                     "speedup_vs_plain": res["plain"] / res["batched_persistent"],
+                                     "equal_to_batched": bool(torch.equal(Xq, Xm)),
+                                     "launch": "the same count in one persistent cooperative launch over (split, "
+                                               "task or cut row, colouring tile) items, dependency levels separated "
+                                               "by a device-wide barrier"}
     if args.instances:
         out["instances_persistent"] = {"value": units / res["instances_persistent"],
                                        "ms": res["instances_persistent"] * 1e3,
@@ -997,6 +1000,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=290.0)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the batched leg's persistent (cooperative) launch, e.g. under a kernel trace")
     ap.add_argument("--instances", action="store_true",
                     help="also time the instance batches (704 instances in one or a few launches)")
     ap.add_argument("--only-packed-compare", action="store_true",
