@@ -310,11 +310,60 @@ __device__ void gather_fold_narrow(const StepParams& S, int64_t beg, int64_t end
     }
 }
 
-// neighbour sum of a segment for p >= 2 (NARROW = G lanes per row, or 0 for the general path)
+// Neighbour sum of the 2-vertex passive table (p = 2). Entry j of a neighbour u's row is the number
+// of u's neighbours of the j-th colour other than col(u) (Eq. 1 for an edge), so every term, and
+// every partial sum of N, is an integer below the number of CSR entries: exact in any order. The
+// terms therefore go to N by LDS atomic adds in whatever order they arrive, and each 64-entry block
+// issues all of its row loads (16 lanes per row, four rows per load instruction) before its first
+// add; the sums are bit for bit those of the ordered paths. ft (LDS, k x 16 entries) receives the
+// N position of every (neighbour colour, entry) for this centre colour, or kNoSlot.
+__device__ void gather_p2(const StepParams& S, int64_t beg, int64_t end, int cv, double* N, uint16_t* ft,
+                          int lane) {
+    const int k = S.k;
+    const int Wp = S.Wp;
+    const int g = lane >> 4, j = lane & 15;
+    for (int t = lane; t < k * 16; t += kWave) {
+        const int c = t >> 4, jj = t & 15;
+        uint16_t f = kNoSlot;
+        if (jj < Wp && c != cv) {
+            const int xpos = cv - (cv > c ? 1 : 0);
+            if (((S.mask[jj] >> xpos) & 1) == 0) f = S.fold[((int64_t)c * k + cv) * Wp + jj];
+        }
+        ft[t] = f;
+    }
+    wave_sync_lds();
+    const double* Pb = S.P + (int64_t)class_slot(S, cv) * S.class_stride;
+    for (int64_t e0 = beg; e0 < end; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        const bool valid = e < end;
+        const int u = valid ? S.col[e] : 0;
+        const int cu = valid ? (int)(S.ecol ? S.ecol[e] : S.colour[(int64_t)u * S.cstride]) : 255;
+        const int cnt = (end - e0 < kWave) ? (int)(end - e0) : kWave;
+        double x[16];
+        int tq[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = q * 4 + g;
+            const int ui = __shfl(u, i < cnt ? i : 0);
+            const int ci = __shfl(cu, i < cnt ? i : 0);
+            const bool row = i < cnt && ci < k && ci != cv && j < Wp;
+            x[q] = row ? Pb[(int64_t)ui * S.pstride + j] : 0.0;
+            tq[q] = row ? (int)ft[ci * 16 + j] : (int)kNoSlot;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (tq[q] != (int)kNoSlot)
+                __hip_atomic_fetch_add(N + tq[q], x[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+}
+
+// neighbour sum of a segment for p >= 2 (NARROW = G lanes per row, 2 for the 2-vertex table, or 0
+// for the general path)
 template <int J, int NARROW>
 __device__ __forceinline__ void gather_rows(const StepParams& S, int64_t beg, int64_t end, int cv, double* N,
                                             int lane) {
-    if constexpr (NARROW > 0) gather_fold_narrow<NARROW>(S, beg, end, cv, N, N + S.stage_off, lane);
+    if constexpr (NARROW == 2) gather_p2(S, beg, end, cv, N, reinterpret_cast<uint16_t*>(N + S.stage_off), lane);
+    else if constexpr (NARROW > 0) gather_fold_narrow<NARROW>(S, beg, end, cv, N, N + S.stage_off, lane);
     else gather_fold<J>(S, beg, end, cv, N, lane);
 }
 
@@ -881,13 +930,15 @@ struct SplitLaunch {
 
 static hipError_t split_geometry(StepParams* Sp, SplitLaunch* L) {
     StepParams& S = *Sp;
-    // narrow passive rows take G lanes per row (a stage of 64 rows in LDS) unless a width is forced
-    const int narrow = (S.p >= 2 && S.cols_per_lane == 0 && S.Wp <= 32) ? (S.Wp <= 16 ? 16 : 32) : 0;
+    // the 2-vertex table has its own path (a table of k x 16 fold positions in LDS); other narrow
+    // passive rows take G lanes per row (a stage of 64 rows in LDS) unless a width is forced
+    const bool p2 = S.p == 2 && S.cols_per_lane == 0 && S.Wp <= 16;
+    const int narrow = (!p2 && S.p >= 2 && S.cols_per_lane == 0 && S.Wp <= 32) ? (S.Wp <= 16 ? 16 : 32) : 0;
     S.a_off = split_a_off(S.Nw);
     S.stage_a = split_stage_a(S.Nw, S.Wa, S.a) ? 1 : 0;
     S.lds_wave = split_lds_wave(S.Nw, S.Wa, S.a);
     S.stage_off = S.lds_wave;
-    S.lds_wave += narrow * kWave;
+    S.lds_wave += p2 ? kMaxK * 16 * (int)sizeof(uint16_t) / (int)sizeof(double) : narrow * kWave;
     if ((size_t)S.lds_wave * sizeof(double) > 160 * 1024) return hipErrorInvalidConfiguration;
     const int waves_per_block = waves_for_lds(S.lds_wave);
     const int threads = waves_per_block * kWave;
@@ -895,7 +946,8 @@ static hipError_t split_geometry(StepParams* Sp, SplitLaunch* L) {
     const size_t lds = (size_t)S.lds_wave * waves_per_block * sizeof(double);
     const int J = (S.p >= 2) ? launch_J(S.Wp, S.cols_per_lane) : 1;
     const void* fn = nullptr;
-    if (narrow == 16) fn = (const void*)k_split<1, 16>;
+    if (p2) fn = (const void*)k_split<1, 2>;
+    else if (narrow == 16) fn = (const void*)k_split<1, 16>;
     else if (narrow == 32) fn = (const void*)k_split<1, 32>;
     else switch (J) {
         case 1: fn = (const void*)k_split<1, 0>; break;
