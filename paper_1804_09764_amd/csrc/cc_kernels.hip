@@ -576,7 +576,18 @@ __global__ __launch_bounds__(256) void k_project(const double* __restrict__ P, i
         if (cu >= k) continue;
         const double* prow = P + u * pstride;
         if constexpr (STAGE) {
-            for (int j = lane; j < W; j += kWave) row_sh[j] = prow[j];
+            // every load of the row in flight before the first store to the stage
+            double t[kProjStage / kWave];
+#pragma unroll
+            for (int q = 0; q < kProjStage / kWave; ++q) {
+                const int j = q * kWave + lane;
+                t[q] = j < W ? prow[j] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < kProjStage / kWave; ++q) {
+                const int j = q * kWave + lane;
+                if (j < W) row_sh[j] = t[q];
+            }
             wave_sync_lds();
         }
         for (int c = 0; c < k; ++c) {
