@@ -527,9 +527,10 @@ __device__ __forceinline__ void do_hub(const StepParams& S, int64_t t, double* N
 // Tasks (chunks of cut rows first, then ranges of light rows, all of about `chunk` entries) are
 // dealt to the persistent wavefronts round-robin: no shared counter, one fixed owner per task.
 // The second bound is the minimum wavefronts per SIMD the register allocation must allow: the
-// 16-lane narrow variant would otherwise sit just above the 128-register step to four.
+// 16-lane narrow variant and the 8-double gather would otherwise sit just above the 128-register
+// step to four (the 8-double gather: 129 registers and three wavefronts; bounded, 6 % faster).
 template <int J, int NARROW>
-__global__ __launch_bounds__(256, (NARROW == 16 ? 4 : 1)) void k_split(StepParams S) {
+__global__ __launch_bounds__(256, ((NARROW == 16 || J == 8) ? 4 : 1)) void k_split(StepParams S) {
     extern __shared__ double lds[];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
