@@ -23,7 +23,8 @@ def _close(gpu, ref):
 
 
 @pytest.mark.parametrize("k,B,tune", [(5, 7, {}), (7, 64, {}), (7, 33, {"hub_threshold": 64, "chunk": 64}),
-                                      (6, 16, {"packed_tile": 128})])
+                                      (6, 16, {"packed_tile": 128}), (5, 1, {}),
+                                      (6, 130, {"hub_threshold": 64, "chunk": 64})])
 def test_persistent_equals_launch_per_split_and_oracle(dev, k, B, tune):
     import torch
     import paper_1804_09764_amd as cc
