@@ -411,9 +411,10 @@ cc_status cc_count_packed_multi_persistent_workspace_bytes(const cc_multi* multi
  * the same tiles), in one persistent launch over (split, task or cut row, colouring tile) items:
  * the outer loop of Algorithm 1 over B colourings and every template's splits of Eq. 1
  * (Section 2.1), the neighbour lists cut into tasks as in Section 3.3, Algorithm 4. The splits are
- * grouped by dependency level; each level's tasks, then its cut-row finishes, are dealt to the
- * resident workgroups, with a device-wide barrier between phases (a cooperative launch, so every
- * workgroup is resident and the barrier cannot wait on one that never runs). Tables are placed so
+ * grouped by dependency level; the resident workgroups take each level's tasks, then its cut-row
+ * finishes, one item block at a time from a per-phase counter in the workspace, with a device-wide
+ * barrier between phases (a cooperative launch, so every workgroup is resident and the barrier
+ * cannot wait on one that never runs). Tables are placed so
  * that the splits of one level never share memory. Then the per-template root sums.
  * Every split must run the packed kernels (rows of at most 64 entries per colouring: templates of
  * up to 7 vertices, or wider templates whose splits stay narrow); CC_ERANGE otherwise. A barrier
