@@ -328,8 +328,11 @@ def bench(args):
         else:
             cc.count(P, G, colours, workspace=ws, out=X)
 
+    X0 = None  # the counts of the first warm-up step's colourings (the packed leg's reference)
     for i in range(args.warmup):
         step(i)
+        if i == 0:
+            X0 = X.clone()
     torch.cuda.synchronize()
     P.profile(True)
     torch.cuda.synchronize()
@@ -416,7 +419,11 @@ def bench(args):
         row_ptr, col = rp_d.cpu().numpy(), col_d.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(row_ptr, col, T, target_s=args.cpu_seconds)
         del row_ptr, col
-    del G, ws, rp_d, col_d
+    del ws
+    torch.cuda.empty_cache()
+    if args.packed_compare > 0 and not packed:
+        out["packed_vs_plain"] = packed_leg(P, G, k, args, X0, elapsed / args.steps / B * 1e3)
+    del G, rp_d, col_d
     torch.cuda.empty_cache()
     if not args.no_batched:
         print("[bench] plain vs batched", file=sys.stderr, flush=True)
@@ -532,6 +539,45 @@ def packed_compare(args):
                 "packed_ms_per_colouring": res["packed"], "packed_over_plain": res["packed"] / res["plain"],
                 "agree": agree})
     return out
+
+
+def packed_leg(P, G, k, args, X0, plain_ms):
+    """The step's first colourings counted packed (as many as fit in 85 % of the free HBM, at most
+    --packed-compare) against the plain count: its time per colouring in the timed steps, and its
+    values for the same colourings (the first warm-up step; exact below 2^53, 1e-12 relative
+    above). Reports whether packing the step's colourings would pay on this workload."""
+    import numpy as np
+    import torch
+
+    import paper_1804_09764_amd as cc
+    dev = torch.device("cuda:0")
+    free = torch.cuda.mem_get_info(dev)[0]
+    b = args.packed_compare
+    while b > 0 and cc.count_packed_workspace_bytes(P, G, b) > 0.85 * free:
+        b -= 1
+    if b == 0:
+        return {"fits": False, "plain_ms_per_colouring": plain_ms}
+    C = cc.colour(G, k, seed=args.seed, first_iter=0, B=b)
+    ws = cc.Workspace()
+    Xq = torch.empty(b, dtype=torch.float64, device=dev)
+    cc.count_packed(P, G, C, workspace=ws, out=Xq)  # warm-up (and the workspace's allocation)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cc.count_packed(P, G, C, workspace=ws, out=Xq)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / b
+    agree = None
+    if X0 is not None:
+        xq, xp = Xq.cpu().numpy(), X0[:b].cpu().numpy()
+        small = xp < 2.0 ** 53
+        agree = bool(np.array_equal(xq[small], xp[small]) and np.all(np.abs(xq - xp)[~small] <= 1e-12 * xp[~small]))
+    del ws
+    torch.cuda.empty_cache()
+    print(f"[bench] packed: {ms:.1f} ms per colouring ({b} colourings) against plain {plain_ms:.1f} ms",
+          file=sys.stderr, flush=True)
+    return {"fits": True, "colourings": b, "packed_ms_per_colouring": ms, "plain_ms_per_colouring": plain_ms,
+            "packed_over_plain": ms / plain_ms, "agree_with_plain": agree,
+            "packed_workspace_GB": cc.count_packed_workspace_bytes(P, G, b) / 1e9}
 
 
 def budget_leg(P, G, k, args, full_bytes, ws):
@@ -1004,6 +1050,9 @@ def main():
                     help="skip the batched leg's persistent (cooperative) launch, e.g. under a kernel trace")
     ap.add_argument("--instances", action="store_true",
                     help="also time the instance batches (704 instances in one or a few launches)")
+    ap.add_argument("--packed-compare", type=int, default=2,
+                    help="also count this many of the step's colourings packed (fewer if they do not fit; "
+                         "0: skip) and compare with the plain count")
     ap.add_argument("--only-packed-compare", action="store_true",
                     help="packed counts of the largest colouring batch that fits against plain counts "
                          "of the same colourings, on --workload")
