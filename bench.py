@@ -67,6 +67,20 @@ def kernel_hash(workload: str = DEFAULT_WORKLOAD) -> str:
     return h.hexdigest()[:16]
 
 
+def reference_plan_model(T, nnz, colourings, seconds):
+    """The reference partition (centre root, cut smallest child) behind the CSEU units, and two
+    figures reported beside them, never mixed with them: the combine's multiply-adds per vertex,
+    sum over splits of C(k, s) C(s, a), and the paper's per-neighbour cost model, the same sum per
+    CSR entry (C(k, |T_i|) C(|T_i|, |T_i'|) per split, Section 3.2), as operations per second."""
+    import paper_1804_09764_amd as cc
+    ref = cc.Plan(T, flags=cc.CC_PLAN_CENTRE_SMALLEST, bind=False)
+    k = ref.k
+    fma = sum(math.comb(k, s) * math.comb(s, a) for (s, a, _) in ref.splits)
+    return {"splits": [list(x) for x in ref.splits], "units_per_edge": ref.info.units_per_edge,
+            "combine_fma_per_vertex": fma, "paper_model_ops_per_edge": fma,
+            "paper_model_ops_per_s": float(nnz) * fma * colourings / seconds}
+
+
 def widths(k, s, a, p):
     W = lambda t: math.comb(k - 1, t - 1)  # noqa: E731  colour-anchored row width
     return W(p), W(a), W(s)
@@ -411,6 +425,7 @@ def bench(args):
                      "traffic_GBps": (traffic / (avg_ms * 1e-3)) if traffic else None,
                      "traffic_over_method": (traffic * 1e9 / alg) if traffic else None},
         "splits": per_split,
+        "reference_plan": reference_plan_model(T, nnz, B * args.steps, elapsed),
         "X_last": [float(x) for x in Xh],
     }
     if args.budget_frac > 0:

@@ -135,3 +135,14 @@ def test_summarize_pmc_sums_the_dominant_split(tmp_path, monkeypatch):
     assert res["copy_fetch_factor"] == 2.0 and res["copy_write_factor"] == 1.0
     assert res["traffic_bytes_per_launch"] == 300.0 * 1024 * 2 + 30.0 * 1024
     assert res["kernels"] == ["k_hub_finish", "k_project", "k_split"]
+
+
+def test_reference_plan_model_on_the_3_path():
+    """The 3-path rooted at its centre: splits (2, 1, 1) then (3, 2, 1); the combine's multiply-adds
+    per vertex are C(3,2) C(2,1) + C(3,3) C(3,2) = 9, and the CSEU units per edge 1 + 1 = 2."""
+    import inputs
+    r = bench.reference_plan_model(inputs.path_tree(3), nnz=10, colourings=2, seconds=1.0)
+    assert sorted(tuple(x) for x in r["splits"]) == [(2, 1, 1), (3, 2, 1)]
+    assert r["combine_fma_per_vertex"] == 9
+    assert r["units_per_edge"] == 2
+    assert r["paper_model_ops_per_s"] == 10 * 9 * 2
