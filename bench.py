@@ -941,7 +941,7 @@ def dispatch_sequence(P, G, proj):
 
 def summarize_pmc(args):
     """rocprofv3 --pmc output (counter_collection.csv of a FETCH_SIZE run and of a WRITE_SIZE run)
-    -> gpurun_out/pmc_<workload>.json: the bytes one colouring's dominant split moves (all of its
+    -> pmc_<workload>.json (or --out): the bytes one colouring's dominant split moves (all of its
     kernels: row copies, passes, cut-row finish), scaled by what the same counters read for a plain
     copy of known size. Dispatches are matched to splits by cc_count's launch sequence
     (dispatch_sequence, written by the profiled bench run with --dispatch-map)."""
@@ -991,7 +991,7 @@ def summarize_pmc(args):
            "copy_fetch_factor": f_factor, "copy_write_factor": w_factor,
            "traffic_bytes_per_launch": fetch_kib * 1024.0 * f_factor + write_kib * 1024.0 * w_factor,
            "command": args.command}
-    path = args.out or os.path.join(ROOT, "gpurun_out", f"pmc_{args.workload}.json")
+    path = args.out or f"pmc_{args.workload}.json"
     json.dump(res, open(path, "w"), indent=1)
     print(json.dumps(res))
 
