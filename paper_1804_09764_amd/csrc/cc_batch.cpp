@@ -91,8 +91,9 @@ cc_status cc_batch_create(int32_t n_inst, const cc_instance* inst, uint32_t flag
                 if (sp.p >= 2)
                     B->J = std::max(B->J, cc::pick_J(sp.Wp, G->cols_per_lane));
                 B->lds_wave = std::max(B->lds_wave, cc::split_lds_wave(sp.Nw, sp.Wa, sp.a));
-                // level mode launches each split's tasks with the kernel a plain count uses
-                // (all variants sum in the same order); cut-row finishes run in variant 0
+                // level mode launches each split's tasks with the kernel a plain count uses (all
+                // variants give the same bits: the same order of terms, or for the 2-vertex table
+                // exact integer sums); cut-row finishes run in variant 0
                 const int var = cc::split_variant(sp.p, sp.Wp, G->cols_per_lane);
                 const int base = cc::split_lds_wave(sp.Nw, sp.Wa, sp.a);
                 for (size_t q = (size_t)(G->n_hubs > 0 ? last[j] - 1 : last[j]); q <= (size_t)last[j]; ++q) {

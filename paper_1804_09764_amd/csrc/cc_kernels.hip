@@ -639,7 +639,7 @@ __global__ __launch_bounds__(512) void k_batch_inst(const SegDesc* __restrict__ 
         for (int q = range.first; q < range.first + range.count; ++q) {
             const SegDesc& D = segs[q];
             double* Ash = N + D.S.a_off;
-            for (int64_t t = wib; t < D.n_items; t += wpb) {
+            for (int64_t t = __builtin_amdgcn_readfirstlane(wib); t < D.n_items; t += wpb) {
                 if (D.phase == 0) do_task<J, 0>(D.S, t, N, Ash, lane);
                 else do_hub(D.S, t, N, Ash, lane);
             }
@@ -661,12 +661,15 @@ __global__ __launch_bounds__(256, (NARROW == 16 ? 4 : 1)) void k_batch_level(con
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
     int seg = seg_lo;
     int64_t s_begin = segs[seg].item_start, s_end = s_begin + segs[seg].n_items;
-    for (int64_t t = item_lo + (int64_t)blockIdx.x * wpb + wib; t < item_hi; t += n_waves) {
+    // item and segment indices are wave-uniform: kept in scalar registers
+    for (int64_t t = item_lo + (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(wib); t < item_hi;
+         t += n_waves) {
         while (t >= s_end && seg + 1 < seg_hi) {  // items only increase: walk forward
             ++seg;
             s_begin = segs[seg].item_start;
             s_end = s_begin + segs[seg].n_items;
         }
+        seg = __builtin_amdgcn_readfirstlane(seg);
         const SegDesc& D = segs[seg];
         double* Ash = N + D.S.a_off;
         if (D.phase == 0) do_task<J, NARROW>(D.S, t - s_begin, N, Ash, lane);
@@ -1021,9 +1024,11 @@ hipError_t launch_split(StepParams S, int n_cu, hipStream_t st, hipEvent_t mid) 
 }
 
 // kernel variant of a split: 0..3 = general path with 1, 2, 4, 8 doubles per lane; 4, 5 = narrow
-// rows with 16 or 32 lanes per row (the choice launch_split makes for a plain count)
+// rows with 16 or 32 lanes per row; 6 = the 2-vertex table's path (the choice launch_split makes
+// for a plain count)
 int split_variant(int p, int Wp, int cols_per_lane) {
     if (p < 2) return 0;
+    if (p == 2 && cols_per_lane == 0 && Wp <= 16) return 6;
     if (cols_per_lane == 0 && Wp <= 16) return 4;
     if (cols_per_lane == 0 && Wp <= 32) return 5;
     switch (pick_J(Wp, cols_per_lane)) {
@@ -1034,7 +1039,10 @@ int split_variant(int p, int Wp, int cols_per_lane) {
     }
 }
 
-int variant_stage(int variant) { return variant == 4 ? 16 * kWave : variant == 5 ? 32 * kWave : 0; }
+int variant_stage(int variant) {
+    if (variant == 6) return kMaxK * 16 * (int)sizeof(uint16_t) / (int)sizeof(double);
+    return variant == 4 ? 16 * kWave : variant == 5 ? 32 * kWave : 0;
+}
 
 template <int J, int NARROW>
 static hipError_t launch_level_t(const SegDesc* segs_dev, int seg_lo, int seg_hi, int64_t item_lo, int64_t item_hi,
@@ -1066,6 +1074,7 @@ hipError_t launch_batch_level(const SegDesc* segs_dev, int seg_lo, int seg_hi, i
         case 3: return launch_level_t<8, 0>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
         case 4: return launch_level_t<1, 16>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
         case 5: return launch_level_t<1, 32>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
+        case 6: return launch_level_t<1, 2>(segs_dev, seg_lo, seg_hi, item_lo, item_hi, lds_wave, n_cu, st);
         default: return hipErrorInvalidValue;
     }
 }
