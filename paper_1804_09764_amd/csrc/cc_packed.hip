@@ -228,14 +228,14 @@ __device__ void grid_barrier(unsigned* bar, unsigned nblocks) {
     __syncthreads();
 }
 
-// The phases in order (even: the tasks of a dependency level, odd: its cut-row finishes; an item is
-// one colouring tile of a task or cut row). Item
-// blocks are taken from a per-phase counter (bar[3 + ph], zero at launch): a workgroup that ends
-// its block early takes the next one, so the phase ends about one block after the first
-// workgroup runs out of work, whatever the spread of item costs (light-row ranges of many small
-// rows cost several times a range of one large row). The workgroup stages the block's split maps
-// in LDS when the split changes, and each of its wavefronts runs one item of the block. Which
-// workgroup runs an item changes nothing in its arithmetic.
+// The phases in order (even: the tasks of a dependency level, odd: its cut-row finishes; an item
+// is one colouring tile of a task or cut row). Item blocks are taken from a per-phase counter
+// (bar[3 + ph], zero at launch): a workgroup that ends its block early takes the next one, so the
+// phase ends about one block after the first workgroup runs out of work, whatever the spread of
+// item costs (light-row ranges of many small rows cost several times a range of one large row).
+// The workgroup stages the block's split maps in LDS when the split changes, and each of its
+// wavefronts runs one item of the block. Which workgroup runs an item changes nothing in its
+// arithmetic.
 template <int JP>
 __global__ __launch_bounds__(256, 3) void k_pmulti(const PSeg* __restrict__ segs, const PItemBlock* __restrict__ blocks,
                                                 const PPhase* __restrict__ phases, int n_phases, int tab_doubles,
